@@ -1,0 +1,234 @@
+"""Benchmark: points located + interpolated per second on one MI355X.
+
+Workload (one step = findpts + findpts_eval of every query point): the
+cylinder-in-box annulus, 16,384 curved hexahedra of order 7 (64 azimuthal x
+16 radial x 16 axial, rho in [0.5, 1], z in [0, 1], nodes at exact polar
+positions), 1,010,000 query points (1e6 area-uniform in the annulus plus 1 %
+outside it), 4 float64 fields given as random polynomials of total degree 7.
+All inputs are synthetic, seeded, and resident in HBM before timing starts.
+
+Prints one JSON line.  Besides the throughput it reports:
+  roofline      the Newton (locate) kernel, bound by float64 vector ALU:
+                algorithmic flops per launch / its mean duration (HIP events
+                recorded by the library on the launch stream) vs 78.6 TFLOP/s
+  cpu_baseline  the CPU oracle timed on a bounded sample of the same points
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6
+PROFILE_PMC = os.path.join(ROOT, "profiles", "locate_annulus_c2_pmc.txt")
+
+
+def locate_flops_per_point(N, c, K):
+    """Algorithmic float64 flops of one point's location: per candidate, the
+    closest-node scan (7V), K Newton iterations each evaluating the map and
+    its Jacobian by sum factorisation (12V + 18 n1^2 + 24 n1) and one final
+    map evaluation (6 (V + n1^2 + n1))."""
+    n1 = N + 1
+    V = n1 ** 3
+    return c * (7 * V + K * (12 * V + 18 * n1 ** 2 + 24 * n1) + 6 * (V + n1 ** 2 + n1))
+
+
+def eval_flops_per_point(N, nf):
+    n1 = N + 1
+    return nf * 2 * (n1 ** 3 + n1 ** 2 + n1)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("fp_locate.hip", "fp_basis.h"):
+        with open(os.path.join(ROOT, "paper_1811_04891_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per locate launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    if not os.path.exists(PROFILE_PMC):
+        return None
+    vals = {}
+    for line in open(PROFILE_PMC):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(mesh, pts, fields, target_s=10.0):
+    import numpy as np
+
+    import oracle
+    om = oracle.OracleMesh.from_mesh(mesh, 1e-12)
+    nthreads = len(os.sched_getaffinity(0))
+    cores = oracle.threads(nthreads)
+    p = pts.cpu().numpy()
+    probe = p[: 4000]
+    t = time.perf_counter()
+    om.findpts(probe, nthreads=nthreads)
+    dt = time.perf_counter() - t
+    n = int(min(len(p), max(4000, 4000 * target_s / max(dt, 1e-3))))
+    sample = p[:n]
+    hf = [f.cpu().numpy() for f in fields]
+    t = time.perf_counter()
+    code, el, rst, _ = om.findpts(sample, nthreads=nthreads)
+    om.eval(code, el, rst, hf, nthreads=nthreads)
+    t_loc = time.perf_counter() - t
+    c = om.last_stats[0] / n
+    K = om.last_stats[1] / max(om.last_stats[0], 1)
+    return {"n": n, "seconds": t_loc, "cores": cores, "c": c, "K": K, "om": om,
+            "sample_code": code}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--points", type=int, default=1_000_000,
+                    help="in-annulus points (1 %% more are placed outside)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+              "the path shards by replicating the mesh and splitting the points, "
+              "which is not built here.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as w
+    from paper_1811_04891_amd import findpts as fp
+
+    dev = torch.device("cuda:0")
+    mesh_cpu = w.annulus_c2()
+    mesh = mesh_cpu.to(dev)
+    pts = w.queries_c2(n_in=args.points).to(dev)
+    P = pts.shape[0]
+    fields, _ = w.poly_fields(mesh, 4, degree=7, seed=2)
+    N = mesh.N
+    print(f"# setup: E={mesh.E} N={N} points={P} fields=4", file=sys.stderr, flush=True)
+
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    h = fp.findpts_setup(mesh.x, mesh.y, mesh.z, N, tol=1e-12, max_points=1 << 20)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    code = torch.empty(P, dtype=torch.int32, device=dev)
+    el = torch.empty(P, dtype=torch.int32, device=dev)
+    rst = torch.empty((P, 3), dtype=torch.float64, device=dev)
+    d2 = torch.empty(P, dtype=torch.float64, device=dev)
+    out = torch.empty((4, P), dtype=torch.float64, device=dev)
+
+    def step():
+        fp.findpts(h, pts, None, code, el, rst, d2)
+        fp.findpts_eval(h, code, el, rst, fields, out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    fp.findpts_stats(h, reset=True)
+    fp.findpts_timing(h, True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    fp.findpts_timing(h, False)
+    tim = fp.findpts_timing_read(h)
+    pairs, iters, located = fp.findpts_stats(h)
+    ms_per_step = total_ms / args.steps
+    value = P / (ms_per_step / 1e3)
+    print(f"# {ms_per_step:.3f} ms/step, {value:.4g} points/s; kernels {tim}", file=sys.stderr,
+          flush=True)
+    codes = np.bincount(code.cpu().numpy(), minlength=3)
+
+    cb = None
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        cb = cpu_baseline(mesh_cpu, pts, fields, args.cpu_seconds)
+    c_gpu = pairs / max(located, 1)
+    K_gpu = iters / max(pairs, 1)
+    c_alg, K_alg = (cb["c"], cb["K"]) if cb else (c_gpu, K_gpu)
+    loc_ms = tim["locate_kernel"][0] / max(tim["locate_kernel"][1], 1)
+    ev_ms = tim["eval_kernel"][0] / max(tim["eval_kernel"][1], 1)
+    alg_flops = P * locate_flops_per_point(N, c_alg, K_alg)
+    achieved = alg_flops / (loc_ms / 1e3) / 1e12
+    traffic = read_traffic()
+    rec = {
+        "metric": "points located+interpolated/sec, FP64 vs mixed; p50/p99 request latency",
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "annulus_c2: 16,384 curved hexes N=7 (64x16x16, exact arcs), "
+                        f"{P} query points (1% outside), 4 f64 fields; findpts+findpts_eval, FP64",
+            "E": mesh.E, "N": N, "points": P, "fields": 4, "precision": "fp64",
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "k_locate (trust-region Newton, one wavefront per element)",
+            "achieved": achieved,
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS,
+            "traffic": traffic,
+            "alg_flops_per_launch": alg_flops,
+            "launch_ms": loc_ms,
+            "candidates_per_point": c_alg,
+            "newton_iters_per_candidate": K_alg,
+        },
+        "breakdown_ms": {
+            "locate_kernel": loc_ms,
+            "eval_kernel": ev_ms,
+            "findpts": tim["findpts"][0] / max(tim["findpts"][1], 1),
+            "findpts_eval": tim["findpts_eval"][0] / max(tim["findpts_eval"][1], 1),
+            "setup_s": setup_s,
+        },
+        "gpu_counts": {"pairs_per_point": c_gpu, "newton_iters_per_pair": K_gpu,
+                       "codes": codes.tolist()},
+    }
+    if cb:
+        rec["cpu_baseline"] = {
+            "value": cb["n"] / cb["seconds"],
+            "unit": "points/s",
+            "cores": cb["cores"],
+            "kind": "oracle",
+            "sample": f"first {cb['n']} of the same {P} query points, findpts + "
+                      f"findpts_eval of the 4 fields (plain C double, OpenMP), "
+                      f"{cb['seconds']:.1f} s",
+        }
+    print(json.dumps(rec), flush=True)
+    h.free()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,189 @@
+/*
+ * findpts.h -- C ABI of the MI355X (gfx950) findpts / findpts_eval library.
+ *
+ * The library locates arbitrary points x* in a mesh of curved isoparametric
+ * hexahedral spectral elements of order N and interpolates nodal fields at
+ * the located points (Mittal, Dutta & Fischer, "Nonconforming Schwarz-
+ * spectral element methods for incompressible flow", Section 2.1: findpts
+ * determines the computational coordinates (e, r, s, t) of any x* and tells
+ * whether it was found inside an element, on a border, or not at all;
+ * findpts_eval interpolates a scalar field at those coordinates; all meshes
+ * are posted at setup with a session-id discriminator and a distance-to-
+ * boundary discriminator).  The processor index of the paper is dropped:
+ * one GPU holds the whole mesh.
+ *
+ * Conventions for every call:
+ *   - Pointers are DEVICE pointers (e.g. the data_ptr of a torch CUDA
+ *     tensor) unless the parameter name starts with h_ (host memory).
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue on
+ *     it and return without waiting unless stated otherwise.
+ *   - Return value: FP_OK (0) or a negative fp_status.  Nothing aborts or
+ *     exits; fp_last_error() gives a message for the calling thread.
+ *   - A handle is used by one stream at a time.  Calls that overlap on one
+ *     handle race (the serving layer below owns concurrency).
+ *
+ * Node layout of every per-element array (coordinates, fields, delta):
+ *   index i + n1*(j + n1*(k + n1*e)), n1 = N + 1, i the r index (fastest),
+ *   j the s index, k the t index, e the element id.
+ */
+#ifndef FINDPTS_H
+#define FINDPTS_H
+
+#include <stddef.h>
+
+#ifndef FP_API
+#define FP_API __attribute__((visibility("default")))
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fp_handle fp_handle; /* opaque, owned by the library */
+
+enum fp_status {
+    FP_OK = 0,
+    FP_EINVAL = -1, /* NULL / negative / non-finite argument, bad flag      */
+    FP_ENOMEM = -2, /* device allocation failed                              */
+    FP_EHIP = -3,   /* a HIP runtime error; text in fp_last_error()          */
+    FP_ESTATE = -4, /* call not valid in the handle's current state          */
+    FP_ERANGE = -5, /* N outside [1, 15], or a size beyond a stated limit    */
+    FP_EBUSY = -6   /* serving: wait timed out / queue full                  */
+};
+
+/* Status code per point (Section 2.1: found inside an element, on a border,
+ * or not found). */
+enum fp_code {
+    FP_INSIDE = 0,   /* ||x^e(r) - x*|| <= tol * h_e for the returned element */
+    FP_BORDER = 1,   /* candidates exist but none holds x* within tol: the
+                        closest point found (r usually on a face of [-1,1]^3) */
+    FP_NOT_FOUND = 2 /* no candidate element: el = -1, rst = 0, dist2 = +inf  */
+};
+
+enum fp_precision {
+    FP_PREC_FP64 = 0, /* every step in binary64                              */
+    FP_PREC_MIXED = 1 /* binary32 start search and early Newton iterations;
+                         final Newton steps, acceptance, classification,
+                         delta and the returned residual in binary64        */
+};
+
+/*
+ * findpts_setup -- post one mesh (Section 2.1: all meshes are posted to setup
+ * together with the session-id and distance discriminators).
+ *   h            out: new handle (host pointer to a handle pointer).
+ *   x, y, z      node coordinates, each E*(N+1)^3 doubles (layout above).
+ *                Copied into handle-owned memory: the caller may free them
+ *                once `stream` has passed this call.
+ *   E, N         element count (>= 1) and order (1 <= N <= 15).
+ *   tol          inside tolerance relative to the element size h_e (the
+ *                largest per-axis extent of the element's nodes); a point is
+ *                FP_INSIDE when ||x^e(r) - x*|| <= tol * h_e.  0 < tol < 1.
+ *   elem_session E ints (session id per element, >= 0) or NULL (all 0).
+ *   delta        E*(N+1)^3 nodal values of the distance-to-own-boundary
+ *                field, or NULL (then ownership among several inside
+ *                candidates goes to the smallest element id).
+ *   max_points   largest npts handled in one internal pass (>= 1); larger
+ *                findpts / findpts_eval calls are processed in passes.  The
+ *                workspace is sized from it at setup.
+ *   precision    an fp_precision value.
+ * Synchronises `stream` (twice: to size the hash grid and its workspace).
+ * Errors: FP_EINVAL (NULL pointers, E < 1, bad tol/precision/max_points,
+ * non-finite coordinates, detected on the device), FP_ERANGE (N), FP_ENOMEM,
+ * FP_EHIP.  Inverted or degenerate elements are accepted (never rejected).
+ */
+FP_API int findpts_setup(fp_handle **h, const double *x, const double *y,
+                  const double *z, int E, int N, double tol,
+                  const int *elem_session, const double *delta,
+                  int max_points, int precision, void *stream);
+
+/*
+ * findpts -- locate npts points (Section 2.1: hash lookup, elementwise
+ * bounding boxes, trust-region Newton on ||x^e(r) - x*||^2 started from the
+ * closest mapped GLL node; session exclusion and largest-delta ownership).
+ *   pts        npts*3 doubles, x y z interleaved.
+ *   pt_session npts ints or NULL.  A point tagged j >= 0 is searched only in
+ *              elements whose session differs from j; a negative tag (or
+ *              NULL) searches every element.
+ *   code       out, npts ints (fp_code).
+ *   el         out, npts ints: element id, -1 if not found.
+ *   rst        out, npts*3 doubles: reference coordinates in [-1,1]^3.
+ *   dist2      out, npts doubles: ||x^e(rst) - x*||^2 (+inf if not found).
+ * Outputs are in the caller's point order.  Allocates nothing.  npts == 0 is
+ * a no-op.  Non-finite points are FP_NOT_FOUND.
+ */
+FP_API int findpts(fp_handle *h, int npts, const double *pts, const int *pt_session,
+            int *code, int *el, double *rst, double *dist2, void *stream);
+
+/*
+ * findpts_eval -- interpolate nfields scalar fields at located points
+ * (Section 2.1: f(e, r) = sum_ijk F^e_ijk h_i(r) h_j(s) h_k(t)).
+ *   code, el, rst  as returned by findpts (code FP_NOT_FOUND gives NaN).
+ *   h_fields       HOST array of nfields device pointers, each to
+ *                  E*(N+1)^3 doubles; borrowed for the stream-ordered call.
+ *   out            out, nfields*npts doubles, field-major: out[f*npts + p].
+ * Allocates nothing.  Errors: FP_EINVAL (NULL, nfields < 1, an element id
+ * out of range is NOT checked on the device: el must come from findpts).
+ */
+FP_API int findpts_eval(fp_handle *h, int npts, const int *code, const int *el,
+                 const double *rst, int nfields,
+                 const double *const *h_fields, double *out, void *stream);
+
+/* Switch precision (fp_precision) for later calls; FP_EINVAL if unknown.
+ * Mixed precision needs no new allocation: the binary32 geometry copy is
+ * built at setup. */
+FP_API int findpts_set_precision(fp_handle *h, int precision);
+
+/*
+ * findpts_stats -- cumulative counters since setup (or the last reset),
+ * written to host memory: h_counts[0] = (point, candidate element) pairs
+ * examined, h_counts[1] = Newton iterations, h_counts[2] = points located.
+ * Synchronises the device.  reset != 0 zeroes them afterwards.
+ */
+FP_API int findpts_stats(fp_handle *h, long long *h_counts, int reset);
+
+/*
+ * Per-kernel timing with HIP events recorded on the call's stream.
+ * findpts_timing(h, 1) turns recording on; findpts_timing_read fills
+ * h_ms[4] with the summed milliseconds and h_n[4] with the launch counts of
+ * [0] the Newton (locate) kernel, [1] the interpolation kernel,
+ * [2] whole findpts calls, [3] whole findpts_eval calls, then clears them.
+ * findpts_timing_read synchronises the recorded events.
+ */
+FP_API int findpts_timing(fp_handle *h, int enable);
+FP_API int findpts_timing_read(fp_handle *h, double *h_ms, long long *h_n);
+
+/*
+ * Read back setup products to host memory (parity tests):
+ * h_bbox E*6 doubles (xmin xmax ymin ymax zmin zmax), h_size E doubles (h_e);
+ * h_nc[3] hash cells per axis, h_lo[3] grid origin, h_dx[3] cell size,
+ * h_meta[3] = {cell count, stored cell entries, largest cell list}.
+ * findpts_get_cells copies cell_off (ncell+1 ints) and cell_el (nnz ints).
+ * Each synchronises the device.
+ */
+FP_API int findpts_get_bbox(fp_handle *h, double *h_bbox, double *h_size);
+FP_API int findpts_get_hash(fp_handle *h, int *h_nc, double *h_lo, double *h_dx,
+                     long long *h_meta);
+FP_API int findpts_get_cells(fp_handle *h, int *h_cell_off, int *h_cell_el);
+
+/* Device bytes held by the handle (mesh copy, hash, workspace). */
+FP_API int findpts_footprint(const fp_handle *h, size_t *h_bytes);
+
+/* Release the handle after work already enqueued has finished (device-wide
+ * synchronisation).  NULL is a no-op. */
+FP_API int findpts_free(fp_handle *h);
+
+/* Message of the last error on the calling thread ("" if none). */
+FP_API const char *fp_last_error(void);
+
+/*
+ * fp_copy -- plain device-to-device copy kernel of `bytes` bytes (multiple
+ * of 16, 16-byte aligned pointers), used to calibrate bandwidth and hardware
+ * byte counters against a kernel of known traffic.  Enqueued on `stream`.
+ */
+FP_API int fp_copy(const void *src, void *dst, size_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FINDPTS_H */

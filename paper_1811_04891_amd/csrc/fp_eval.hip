@@ -1,0 +1,189 @@
+// findpts_eval: tensor-product Lagrange interpolation of nodal fields at
+// located points (Section 2.1 of the paper).  Points are grouped by element
+// with a counting sort so that one 64-lane wavefront reads each element's
+// field values once (scalar loads) for all of its points.
+#include <cmath>
+
+#include "fp_basis.h"
+#include "fp_internal.h"
+
+namespace fp {
+
+struct FieldPtrs {
+    const double *f[kMaxEvalFields];
+};
+
+struct EvArgs {
+    const int *code;
+    const int *el;
+    const double *rst;
+    int npts;
+    int E;
+    int *cnt;
+    const int *off;
+    int *pos;
+    int *order;
+    double *out;   // field-major, stride npts_total
+    long long ostride;
+    int nf;
+    double *out_all;  // first field of the call, for NaN fill
+    int nf_all;
+};
+
+// Count points per element; not-found points get NaN right away.
+__global__ __launch_bounds__(256) void k_ev_count(EvArgs a)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.npts) return;
+    const int e = a.el[p];
+    if (a.code[p] != FP_NOT_FOUND && e >= 0 && e < a.E) {
+        a.pos[p] = atomicAdd(&a.cnt[e], 1);
+    } else {
+        a.pos[p] = -1;
+        for (int f = 0; f < a.nf_all; ++f) a.out_all[f * a.ostride + p] = NAN;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ev_scatter(EvArgs a)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.npts) return;
+    const int k = a.pos[p];
+    if (k >= 0) a.order[a.off[a.el[p]] + k] = p;
+}
+
+template <int N1>
+__global__ __launch_bounds__(kWave) void k_eval(EvArgs a, FieldPtrs F, const double *__restrict__ basis)
+{
+    constexpr int V = N1 * N1 * N1;
+    const BasisPtr<double> B{as_const(basis)};
+    const int e = blockIdx.x;
+    const int beg = a.off[e], end = a.off[e + 1];
+    if (beg >= end) return;
+    for (int base = beg; base < end; base += kWave) {
+        const int q = base + (int)threadIdx.x;
+        const bool act = q < end;
+        const int p = act ? a.order[q] : 0;
+        double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+        if (act) {
+            r0 = a.rst[3 * (long long)p];
+            r1 = a.rst[3 * (long long)p + 1];
+            r2 = a.rst[3 * (long long)p + 2];
+        }
+        double hr[N1], hs[N1], ht[N1];
+        lagrange<N1>(B, r0, hr);
+        lagrange<N1>(B, r1, hs);
+        lagrange<N1>(B, r2, ht);
+        for (int f = 0; f < a.nf; ++f) {
+            const double v = field_value<N1>(as_const(F.f[f] + (long long)e * V), hr, hs, ht);
+            if (act) a.out[f * a.ostride + p] = v;
+        }
+    }
+}
+
+static hipError_t launch_eval_kernel(int n1, int E, const EvArgs &a, const FieldPtrs &F,
+                                     const double *B, hipStream_t s)
+{
+#define FP_LAUNCH_EVAL(N1) k_eval<N1><<<E, kWave, 0, s>>>(a, F, B)
+    switch (n1) {
+        case 2: FP_LAUNCH_EVAL(2); break;
+        case 3: FP_LAUNCH_EVAL(3); break;
+        case 4: FP_LAUNCH_EVAL(4); break;
+        case 5: FP_LAUNCH_EVAL(5); break;
+        case 6: FP_LAUNCH_EVAL(6); break;
+        case 7: FP_LAUNCH_EVAL(7); break;
+        case 8: FP_LAUNCH_EVAL(8); break;
+        case 9: FP_LAUNCH_EVAL(9); break;
+        case 10: FP_LAUNCH_EVAL(10); break;
+        case 11: FP_LAUNCH_EVAL(11); break;
+        case 12: FP_LAUNCH_EVAL(12); break;
+        case 13: FP_LAUNCH_EVAL(13); break;
+        case 14: FP_LAUNCH_EVAL(14); break;
+        case 15: FP_LAUNCH_EVAL(15); break;
+        case 16: FP_LAUNCH_EVAL(16); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef FP_LAUNCH_EVAL
+    return hipGetLastError();
+}
+
+}  // namespace fp
+
+using namespace fp;
+
+extern "C" int findpts_eval(fp_handle *h, int npts, const int *code, const int *el,
+                            const double *rst, int nfields, const double *const *h_fields,
+                            double *out, void *stream)
+{
+    if (!h) {
+        set_error("findpts_eval: NULL handle");
+        return FP_EINVAL;
+    }
+    if (npts < 0 || nfields < 1) {
+        set_error("findpts_eval: npts < 0 or nfields < 1");
+        return FP_EINVAL;
+    }
+    if (npts == 0) return FP_OK;
+    if (!code || !el || !rst || !h_fields || !out) {
+        set_error("findpts_eval: NULL argument");
+        return FP_EINVAL;
+    }
+    for (int f = 0; f < nfields; ++f)
+        if (!h_fields[f]) {
+            set_error("findpts_eval: NULL field pointer");
+            return FP_EINVAL;
+        }
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    FP_HIP(hipGetDevice(&dev));
+    if (dev != h->device) FP_HIP(hipSetDevice(h->device));
+    for (int start = 0; start < npts; start += h->max_points) {
+        const int n = (npts - start < h->max_points) ? npts - start : h->max_points;
+        hipEvent_t t0 = nullptr, t1 = nullptr, l0 = nullptr, l1 = nullptr;
+        if (h->timing) {
+            t0 = pool_event(h);
+            t1 = pool_event(h);
+            l0 = pool_event(h);
+            l1 = pool_event(h);
+            FP_HIP(hipEventRecord(t0, s));
+        }
+        for (int f0 = 0; f0 < nfields; f0 += kMaxEvalFields) {
+            const int nf = (nfields - f0 < kMaxEvalFields) ? nfields - f0 : kMaxEvalFields;
+            EvArgs a{};
+            a.code = code + start;
+            a.el = el + start;
+            a.rst = rst + 3 * (long long)start;
+            a.npts = n;
+            a.E = h->E;
+            a.cnt = h->ev_cnt;
+            a.off = h->ev_off;
+            a.pos = h->ev_pos;
+            a.order = h->ev_order;
+            a.out = out + (long long)f0 * npts + start;
+            a.ostride = npts;
+            a.nf = nf;
+            a.out_all = out + start;
+            a.nf_all = nfields;
+            FieldPtrs F{};
+            for (int f = 0; f < nf; ++f) F.f[f] = h_fields[f0 + f];
+            const int pb = (n + 255) / 256;
+            if (f0 == 0) {
+                FP_HIP(fill_int(h->ev_cnt, 0, (long long)h->E + 1, s));
+                k_ev_count<<<pb, 256, 0, s>>>(a);
+                FP_HIP(hipGetLastError());
+                FP_HIP(scan_exclusive(h->ev_cnt, h->ev_off, h->E, h->scan_tmp, s));
+                k_ev_scatter<<<pb, 256, 0, s>>>(a);
+                FP_HIP(hipGetLastError());
+                if (h->timing) FP_HIP(hipEventRecord(l0, s));
+            }
+            FP_HIP(launch_eval_kernel(h->n1, h->E, a, F, h->d_basis, s));
+        }
+        if (h->timing) {
+            FP_HIP(hipEventRecord(l1, s));
+            FP_HIP(hipEventRecord(t1, s));
+            h->timed.push_back(TimedPair{1, l0, l1});
+            h->timed.push_back(TimedPair{3, t0, t1});
+        }
+    }
+    return FP_OK;
+}

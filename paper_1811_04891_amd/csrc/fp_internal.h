@@ -1,0 +1,130 @@
+// Internal declarations of the gfx950 findpts library (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/findpts.h"
+
+namespace fp {
+
+constexpr int kMaxN1 = 16;       // N <= 15
+constexpr int kMaxEvalFields = 8; // fields per interpolation launch
+constexpr int kWave = 64;
+
+// GLL nodes z_i and barycentric weights wb_i = 1 / prod_{m != i} (z_i - z_m),
+// passed to kernels by value (kernel arguments are read through the scalar
+// cache).
+struct Basis {
+    double z[kMaxN1];
+    double wb[kMaxN1];
+};
+
+struct Basis32 {
+    float z[kMaxN1];
+    float wb[kMaxN1];
+};
+
+// Hash grid parameters passed by value.
+struct Grid {
+    double lo[3];
+    double hi[3];
+    double inv[3];  // cells per unit length
+    int nc[3];
+};
+
+struct TimedPair {
+    int phase;
+    hipEvent_t a, b;
+};
+
+}  // namespace fp
+
+struct fp_handle {
+    int device = 0;
+    int E = 0, N = 0, n1 = 0, V = 0;
+    double tol = 0.0;
+    int precision = 0;
+    int max_points = 0;
+
+    // mesh (handle-owned)
+    double *geom = nullptr;    // E x 3 x V, element-blocked, r index fastest
+    float *geom32 = nullptr;   // binary32 copy (mixed precision)
+    double *esize = nullptr;   // E: h_e
+    double *bbox = nullptr;    // E x 6
+    int *esess = nullptr;      // E or null
+    double *delta = nullptr;   // E x V or null
+
+    // hash grid
+    fp::Grid grid{};
+    long long ncell = 0, nnz = 0;
+    int max_cell = 0;
+    int *cell_off = nullptr;   // ncell + 1
+    int *cell_el = nullptr;    // nnz
+
+    // findpts workspace, M = max_points, MC = max_cell (>= 1)
+    int MC = 1;
+    int *ncand = nullptr;      // M
+    int *cand_el = nullptr;    // M x MC
+    int *cand_pos = nullptr;   // M x MC, rank of the pair within its element
+    int *elem_cnt = nullptr;   // E + 1
+    int *elem_off = nullptr;   // E + 1
+    int *order = nullptr;      // M x MC pair slots grouped by element
+    double *res = nullptr;     // M x MC x 4: r, s, t, d2
+    double *res_dl = nullptr;  // M x MC: delta at the candidate (if delta)
+    int *res_in = nullptr;     // M x MC: inside flag
+    int *scan_tmp = nullptr;   // block sums of the device scan
+    int scan_tmp_n = 0;
+
+    // findpts_eval workspace
+    int *ev_cnt = nullptr;     // E + 1
+    int *ev_off = nullptr;     // E + 1
+    int *ev_pos = nullptr;     // M
+    int *ev_order = nullptr;   // M
+
+    unsigned long long *stats = nullptr;  // [pairs, newton iterations, points]
+
+    fp::Basis basis{};
+    fp::Basis32 basis32{};
+    double *d_basis = nullptr;   // device copy of basis (z, wb)
+    float *d_basis32 = nullptr;  // device copy of basis32
+    size_t bytes = 0;
+
+    bool timing = false;
+    std::vector<fp::TimedPair> timed;
+    std::vector<hipEvent_t> event_pool;
+};
+
+namespace fp {
+
+void set_error(const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+hipEvent_t pool_event(fp_handle *h);
+
+#define FP_HIP(call)                                         \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return fp::hip_fail(e_, #call); \
+    } while (0)
+
+// Exclusive scan of n ints: out[0..n], out[n] = total.  tmp needs
+// scan_tmp_size(n) ints.
+int scan_tmp_size(long long n);
+hipError_t scan_exclusive(const int *in, int *out, int n, int *tmp,
+                          hipStream_t s);
+
+// Fill n ints with a value (a kernel, so that it may be graph-captured).
+hipError_t fill_int(int *p, int value, long long n, hipStream_t s);
+
+// Launchers (one per kernel family, dispatching on n1).
+hipError_t launch_locate(const fp_handle *h, int npts, const double *pts,
+                         hipStream_t s);
+hipError_t launch_eval(const fp_handle *h, int npts, const double *rst,
+                       int nf, const double *const *fields, double *out,
+                       hipStream_t s);
+
+}  // namespace fp

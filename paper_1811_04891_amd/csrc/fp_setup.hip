@@ -1,0 +1,661 @@
+// findpts_setup and handle management: mesh copy, element boxes (Bernstein
+// hull), hash grid, workspace.  Section 2.1 of the paper: a hash table finds
+// the potential owners of x*, then elementwise bounding boxes filter them.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fp_internal.h"
+
+namespace fp {
+
+// ---------------------------------------------------------------------------
+// Host-side basis tables (GLL nodes, barycentric weights, Bernstein inverse).
+// ---------------------------------------------------------------------------
+
+// Legendre P_n(x) and P_n'(x) by the three-term recurrence.
+static void legendre_pd(int n, double x, double &p, double &dp)
+{
+    double pm = 1.0, pc = x;  // P_0, P_1
+    if (n == 0) { p = 1.0; dp = 0.0; return; }
+    for (int k = 1; k < n; ++k) {
+        double pn = ((2 * k + 1) * x * pc - k * pm) / (k + 1);
+        pm = pc;
+        pc = pn;
+    }
+    p = pc;
+    // (1 - x^2) P_n' = n (P_{n-1} - x P_n); endpoints are not needed here
+    dp = n * (pm - x * pc) / (1.0 - x * x);
+}
+
+// GLL nodes: +-1 and the roots of P_N'.  Roots of P_N' are the interior
+// extrema of P_N; Newton's method is applied to q(x) = (1 - x^2) P_N'(x),
+// whose derivative is -N (N + 1) P_N(x), starting from the Chebyshev-Gauss-
+// Lobatto points; nodes are then symmetrised.
+static void gll_nodes(int N, double *z)
+{
+    z[0] = -1.0;
+    z[N] = 1.0;
+    for (int i = 1; i < N; ++i) {
+        double x = -std::cos(M_PI * i / N);
+        for (int it = 0; it < 60; ++it) {
+            double p, dp;
+            legendre_pd(N, x, p, dp);
+            double q = (1.0 - x * x) * dp;
+            double dq = -N * (N + 1.0) * p;
+            double step = q / dq;
+            x -= step;
+            if (std::fabs(step) <= 1e-17) break;
+        }
+        z[i] = x;
+    }
+    for (int i = 0; i < (N + 1) / 2; ++i) {
+        double a = 0.5 * (z[N - i] - z[i]);
+        z[i] = -a;
+        z[N - i] = a;
+    }
+    if (N % 2 == 0) z[N / 2] = 0.0;
+}
+
+static Basis make_basis(int N)
+{
+    Basis b{};
+    gll_nodes(N, b.z);
+    for (int i = 0; i <= N; ++i) {
+        long double d = 1.0L;
+        for (int m = 0; m <= N; ++m)
+            if (m != i) d *= (long double)b.z[i] - (long double)b.z[m];
+        b.wb[i] = (double)(1.0L / d);
+    }
+    return b;
+}
+
+// Inverse of M[i][k] = C(N,k) u_i^k (1-u_i)^(N-k), u_i = (1 + z_i)/2: maps
+// nodal values to tensor-Bernstein coefficients.  Gauss-Jordan in long
+// double on the host.
+static std::vector<double> bernstein_to_nodal_inverse(int N, const double *z)
+{
+    const int n = N + 1;
+    std::vector<long double> A(n * 2 * n, 0.0L);
+    for (int i = 0; i < n; ++i) {
+        long double u = 0.5L * (1.0L + z[i]), v = 1.0L - u;
+        long double c = 1.0L;  // C(N, k)
+        for (int k = 0; k < n; ++k) {
+            if (k > 0) c = c * (N - k + 1) / k;
+            A[i * 2 * n + k] = c * std::pow(u, (long double)k) * std::pow(v, (long double)(N - k));
+        }
+        A[i * 2 * n + n + i] = 1.0L;
+    }
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < n; ++i)
+            if (std::fabs(A[i * 2 * n + c]) > std::fabs(A[piv * 2 * n + c])) piv = i;
+        if (piv != c)
+            for (int k = 0; k < 2 * n; ++k) std::swap(A[c * 2 * n + k], A[piv * 2 * n + k]);
+        long double d = A[c * 2 * n + c];
+        for (int k = 0; k < 2 * n; ++k) A[c * 2 * n + k] /= d;
+        for (int i = 0; i < n; ++i) {
+            if (i == c) continue;
+            long double f = A[i * 2 * n + c];
+            if (f == 0.0L) continue;
+            for (int k = 0; k < 2 * n; ++k) A[i * 2 * n + k] -= f * A[c * 2 * n + k];
+        }
+    }
+    std::vector<double> out(n * n);
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < n; ++k) out[i * n + k] = (double)A[i * 2 * n + n + k];
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// Kernels.
+// ---------------------------------------------------------------------------
+
+// Copy x, y, z (each E*V) into the element-blocked E x 3 x V layout (and the
+// binary32 copy), flagging non-finite values.
+__global__ __launch_bounds__(256) void k_pack(const double *__restrict__ x,
+                                              const double *__restrict__ y,
+                                              const double *__restrict__ z, long long EV,
+                                              int V, double *__restrict__ geom,
+                                              float *__restrict__ geom32,
+                                              int *__restrict__ bad)
+{
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long stride = (long long)gridDim.x * blockDim.x;
+    int flag = 0;
+    for (; t < EV; t += stride) {
+        long long e = t / V, q = t - e * V;
+        double v0 = x[t], v1 = y[t], v2 = z[t];
+        flag |= !(isfinite(v0) && isfinite(v1) && isfinite(v2));
+        double *g = geom + e * 3 * V + q;
+        g[0] = v0;
+        g[V] = v1;
+        g[2 * V] = v2;
+        if (geom32) {
+            float *g32 = geom32 + e * 3 * V + q;
+            g32[0] = (float)v0;
+            g32[V] = (float)v1;
+            g32[2 * V] = (float)v2;
+        }
+    }
+    if (flag) atomicOr(bad, 1);
+}
+
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// One wave per element: Bernstein coefficients of each coordinate (the
+// inverse nodal-Bernstein matrix applied along r, s, t in LDS), their min and
+// max, the node extents (h_e) and the margin 1e-8 h_e + 1e-14 max|x|.
+__global__ __launch_bounds__(kWave) void k_bbox(const double *__restrict__ geom, int n1,
+                                                const double *__restrict__ binv,
+                                                double *__restrict__ bbox,
+                                                double *__restrict__ esize)
+{
+    extern __shared__ double sh[];
+    const int V = n1 * n1 * n1;
+    double *A = sh, *B = sh + V;
+    __shared__ double Bi[kMaxN1 * kMaxN1];
+    const int e = blockIdx.x, t = threadIdx.x;
+    for (int q = t; q < n1 * n1; q += kWave) Bi[q] = binv[q];
+    double lo[3], hi[3], he = 0.0, amax = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        const double *X = geom + ((long long)e * 3 + c) * V;
+        double mn = INFINITY, mx = -INFINITY;
+        for (int q = t; q < V; q += kWave) {
+            double v = X[q];
+            A[q] = v;
+            mn = fmin(mn, v);
+            mx = fmax(mx, v);
+            amax = fmax(amax, fabs(v));
+        }
+        mn = wave_min(mn);
+        mx = wave_max(mx);
+        he = fmax(he, mx - mn);
+        __syncthreads();
+        for (int q = t; q < V; q += kWave) {  // along r
+            int i = q % n1, rest = q - i;
+            double s = 0.0;
+            for (int l = 0; l < n1; ++l) s = fma(Bi[i * n1 + l], A[rest + l], s);
+            B[q] = s;
+        }
+        __syncthreads();
+        for (int q = t; q < V; q += kWave) {  // along s
+            int i = q % n1, j = (q / n1) % n1, k = q / (n1 * n1);
+            double s = 0.0;
+            for (int l = 0; l < n1; ++l) s = fma(Bi[j * n1 + l], B[i + n1 * (l + n1 * k)], s);
+            A[q] = s;
+        }
+        __syncthreads();
+        double cmn = INFINITY, cmx = -INFINITY;
+        for (int q = t; q < V; q += kWave) {  // along t
+            int ij = q % (n1 * n1), k = q / (n1 * n1);
+            double s = 0.0;
+            for (int l = 0; l < n1; ++l) s = fma(Bi[k * n1 + l], A[ij + n1 * n1 * l], s);
+            cmn = fmin(cmn, s);
+            cmx = fmax(cmx, s);
+        }
+        lo[c] = wave_min(cmn);
+        hi[c] = wave_max(cmx);
+        __syncthreads();
+    }
+    amax = wave_max(amax);
+    if (t == 0) {
+        const double m = 1e-8 * he + 1e-14 * amax;
+        for (int c = 0; c < 3; ++c) {
+            bbox[6 * e + 2 * c] = lo[c] - m;
+            bbox[6 * e + 2 * c + 1] = hi[c] + m;
+        }
+        esize[e] = he;
+    }
+}
+
+// Union of the element boxes (one block).
+__global__ __launch_bounds__(256) void k_gbox(const double *__restrict__ bbox, int E,
+                                              double *__restrict__ out)
+{
+    __shared__ double red[6][256 / kWave];
+    double v[6] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY};
+    for (int e = threadIdx.x; e < E; e += blockDim.x)
+        for (int a = 0; a < 3; ++a) {
+            v[2 * a] = fmin(v[2 * a], bbox[6 * e + 2 * a]);
+            v[2 * a + 1] = fmax(v[2 * a + 1], bbox[6 * e + 2 * a + 1]);
+        }
+    const int w = threadIdx.x / kWave;
+    for (int a = 0; a < 3; ++a) {
+        double mn = wave_min(v[2 * a]), mx = wave_max(v[2 * a + 1]);
+        if ((threadIdx.x & (kWave - 1)) == 0) {
+            red[2 * a][w] = mn;
+            red[2 * a + 1][w] = mx;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int a = 0; a < 3; ++a) {
+            double mn = red[2 * a][0], mx = red[2 * a + 1][0];
+            for (int q = 1; q < (int)(blockDim.x / kWave); ++q) {
+                mn = fmin(mn, red[2 * a][q]);
+                mx = fmax(mx, red[2 * a + 1][q]);
+            }
+            out[2 * a] = mn;
+            out[2 * a + 1] = mx;
+        }
+    }
+}
+
+__device__ __forceinline__ int cell_axis(const Grid &g, int a, double x)
+{
+    double u = (x - g.lo[a]) * g.inv[a];
+    int i = (int)floor(u);
+    return i < 0 ? 0 : (i >= g.nc[a] ? g.nc[a] - 1 : i);
+}
+
+// mode 0: count entries per cell; mode 1: write element ids.
+__global__ __launch_bounds__(256) void k_hash_pass(const double *__restrict__ bbox, int E,
+                                                   Grid g, int mode, int *__restrict__ cnt,
+                                                   const int *__restrict__ off,
+                                                   int *__restrict__ cell_el)
+{
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    const double *b = bbox + 6 * e;
+    int i0 = cell_axis(g, 0, b[0]), i1 = cell_axis(g, 0, b[1]);
+    int j0 = cell_axis(g, 1, b[2]), j1 = cell_axis(g, 1, b[3]);
+    int k0 = cell_axis(g, 2, b[4]), k1 = cell_axis(g, 2, b[5]);
+    for (int k = k0; k <= k1; ++k)
+        for (int j = j0; j <= j1; ++j)
+            for (int i = i0; i <= i1; ++i) {
+                long long c = i + (long long)g.nc[0] * (j + (long long)g.nc[1] * k);
+                int pos = atomicAdd(&cnt[c], 1);
+                if (mode == 1) cell_el[off[c] + pos] = e;
+            }
+}
+
+// Sort each cell list ascending (insertion sort; lists are short) and find
+// the longest list.
+__global__ __launch_bounds__(256) void k_hash_sort(const int *__restrict__ off,
+                                                   int *__restrict__ cell_el, long long ncell,
+                                                   int *__restrict__ maxlen)
+{
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    int b = off[c], n = off[c + 1] - b;
+    int *L = cell_el + b;
+    for (int i = 1; i < n; ++i) {
+        int v = L[i], j = i - 1;
+        while (j >= 0 && L[j] > v) {
+            L[j + 1] = L[j];
+            --j;
+        }
+        L[j + 1] = v;
+    }
+    atomicMax(maxlen, n);
+}
+
+}  // namespace fp
+
+// ---------------------------------------------------------------------------
+// Handle lifetime.
+// ---------------------------------------------------------------------------
+using namespace fp;
+
+static void release(fp_handle *h)
+{
+    void *ptrs[] = {h->d_basis, h->d_basis32, h->geom, h->geom32, h->esize, h->bbox, h->esess, h->delta,
+                    h->cell_off, h->cell_el, h->ncand, h->cand_el, h->cand_pos,
+                    h->elem_cnt, h->elem_off, h->order, h->res, h->res_dl, h->res_in,
+                    h->scan_tmp, h->ev_cnt, h->ev_off, h->ev_pos, h->ev_order, h->stats};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    for (auto &t : h->timed) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (auto ev : h->event_pool) (void)hipEventDestroy(ev);
+    delete h;
+}
+
+template <class T>
+static hipError_t dalloc(fp_handle *h, T **p, size_t count)
+{
+    size_t b = sizeof(T) * (count ? count : 1);
+    hipError_t e = hipMalloc((void **)p, b);
+    if (e == hipSuccess) h->bytes += b;
+    return e;
+}
+
+#define FP_HIP_H(call)                              \
+    do {                                            \
+        hipError_t e_ = (call);                     \
+        if (e_ != hipSuccess) {                     \
+            int rc_ = fp::hip_fail(e_, #call);      \
+            release(h);                             \
+            return rc_;                             \
+        }                                           \
+    } while (0)
+
+extern "C" int findpts_setup(fp_handle **out, const double *x, const double *y,
+                             const double *z, int E, int N, double tol,
+                             const int *elem_session, const double *delta,
+                             int max_points, int precision, void *stream)
+{
+    if (!out || !x || !y || !z) {
+        set_error("findpts_setup: NULL argument");
+        return FP_EINVAL;
+    }
+    *out = nullptr;
+    if (N < 1 || N > kMaxN1 - 1) {
+        set_error("findpts_setup: N must be in [1, 15]");
+        return FP_ERANGE;
+    }
+    if (E < 1 || max_points < 1 || !(tol > 0.0 && tol < 1.0) ||
+        (precision != FP_PREC_FP64 && precision != FP_PREC_MIXED)) {
+        set_error("findpts_setup: need E >= 1, max_points >= 1, 0 < tol < 1, known precision");
+        return FP_EINVAL;
+    }
+    const long long n1 = N + 1, V = n1 * n1 * n1;
+    if ((long long)E * V * 3 > (1LL << 40)) {
+        set_error("findpts_setup: mesh too large");
+        return FP_ERANGE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    fp_handle *h = new fp_handle();
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        set_error("findpts_setup: no HIP device");
+        return FP_EHIP;
+    }
+    h->E = E;
+    h->N = N;
+    h->n1 = (int)n1;
+    h->V = (int)V;
+    h->tol = tol;
+    h->precision = precision;
+    h->max_points = max_points;
+    h->basis = make_basis(N);
+    for (int i = 0; i < kMaxN1; ++i) {
+        h->basis32.z[i] = (float)h->basis.z[i];
+        h->basis32.wb[i] = (float)h->basis.wb[i];
+    }
+    const long long EV = (long long)E * V;
+
+    // mesh copy
+    int *d_flag = nullptr;
+    double *d_g = nullptr;
+    double *d_binv = nullptr;
+    FP_HIP_H(dalloc(h, &h->geom, 3 * EV));
+    FP_HIP_H(dalloc(h, &h->geom32, 3 * EV));  // kept for either precision
+    FP_HIP_H(dalloc(h, &h->esize, E));
+    FP_HIP_H(dalloc(h, &h->bbox, 6 * (size_t)E));
+    FP_HIP_H(dalloc(h, &h->stats, 4));
+    FP_HIP_H(dalloc(h, &h->d_basis, 2 * kMaxN1));
+    FP_HIP_H(dalloc(h, &h->d_basis32, 2 * kMaxN1));
+    FP_HIP_H(hipMemcpyAsync(h->d_basis, &h->basis, sizeof(Basis), hipMemcpyHostToDevice, s));
+    FP_HIP_H(hipMemcpyAsync(h->d_basis32, &h->basis32, sizeof(Basis32), hipMemcpyHostToDevice, s));
+    FP_HIP_H(hipMemsetAsync(h->stats, 0, 4 * sizeof(unsigned long long), s));
+    if (elem_session) {
+        FP_HIP_H(dalloc(h, &h->esess, E));
+        FP_HIP_H(hipMemcpyAsync(h->esess, elem_session, sizeof(int) * E,
+                                hipMemcpyDeviceToDevice, s));
+    }
+    if (delta) {
+        FP_HIP_H(dalloc(h, &h->delta, EV));
+        FP_HIP_H(hipMemcpyAsync(h->delta, delta, sizeof(double) * EV,
+                                hipMemcpyDeviceToDevice, s));
+    }
+    FP_HIP_H(hipMalloc((void **)&d_flag, sizeof(int)));
+    FP_HIP_H(hipMalloc((void **)&d_g, 6 * sizeof(double)));
+    FP_HIP_H(hipMalloc((void **)&d_binv, sizeof(double) * n1 * n1));
+    FP_HIP_H(hipMemsetAsync(d_flag, 0, sizeof(int), s));
+    {
+        long long blocks = std::min<long long>((EV + 255) / 256, 256LL * 64);
+        k_pack<<<(int)blocks, 256, 0, s>>>(x, y, z, EV, (int)V, h->geom, h->geom32, d_flag);
+        FP_HIP_H(hipGetLastError());
+    }
+    std::vector<double> binv = bernstein_to_nodal_inverse(N, h->basis.z);
+    FP_HIP_H(hipMemcpyAsync(d_binv, binv.data(), sizeof(double) * n1 * n1,
+                            hipMemcpyHostToDevice, s));
+    k_bbox<<<E, kWave, 2 * V * sizeof(double), s>>>(h->geom, (int)n1, d_binv, h->bbox,
+                                                     h->esize);
+    FP_HIP_H(hipGetLastError());
+    k_gbox<<<1, 256, 0, s>>>(h->bbox, E, d_g);
+    FP_HIP_H(hipGetLastError());
+    double gb[6];
+    int bad = 0;
+    FP_HIP_H(hipMemcpyAsync(gb, d_g, sizeof gb, hipMemcpyDeviceToHost, s));
+    FP_HIP_H(hipMemcpyAsync(&bad, d_flag, sizeof bad, hipMemcpyDeviceToHost, s));
+    FP_HIP_H(hipStreamSynchronize(s));
+    (void)hipFree(d_binv);
+    (void)hipFree(d_g);
+    if (bad) {
+        (void)hipFree(d_flag);
+        release(h);
+        set_error("findpts_setup: non-finite node coordinates");
+        return FP_EINVAL;
+    }
+
+    // hash grid: about E cells, cell aspect following the extents
+    Grid g{};
+    double ext[3], vol = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        g.lo[a] = gb[2 * a];
+        g.hi[a] = gb[2 * a + 1];
+        ext[a] = g.hi[a] - g.lo[a];
+        if (!(ext[a] > 0.0)) ext[a] = 1e-300;
+        vol *= ext[a];
+    }
+    const double dens = std::cbrt((double)E / vol);
+    for (int a = 0; a < 3; ++a) {
+        double n = std::floor(ext[a] * dens + 0.5);
+        n = std::min(std::max(n, 1.0), 1024.0);
+        g.nc[a] = (int)n;
+        g.inv[a] = g.nc[a] / ext[a];
+    }
+    h->grid = g;
+    h->ncell = (long long)g.nc[0] * g.nc[1] * g.nc[2];
+    int *cnt = nullptr;
+    FP_HIP_H(dalloc(h, &h->cell_off, h->ncell + 1));
+    FP_HIP_H(hipMalloc((void **)&cnt, sizeof(int) * (h->ncell + 1)));
+    int tmpn = std::max(scan_tmp_size(h->ncell), scan_tmp_size((long long)E + 1));
+    h->scan_tmp_n = tmpn;
+    FP_HIP_H(dalloc(h, &h->scan_tmp, tmpn));
+    FP_HIP_H(fill_int(cnt, 0, h->ncell + 1, s));
+    const int eb = (E + 255) / 256;
+    k_hash_pass<<<eb, 256, 0, s>>>(h->bbox, E, g, 0, cnt, nullptr, nullptr);
+    FP_HIP_H(hipGetLastError());
+    FP_HIP_H(scan_exclusive(cnt, h->cell_off, (int)h->ncell, h->scan_tmp, s));
+    int nnz = 0;
+    FP_HIP_H(hipMemcpyAsync(&nnz, h->cell_off + h->ncell, sizeof(int),
+                            hipMemcpyDeviceToHost, s));
+    FP_HIP_H(hipStreamSynchronize(s));
+    h->nnz = nnz;
+    FP_HIP_H(dalloc(h, &h->cell_el, nnz));
+    FP_HIP_H(fill_int(cnt, 0, h->ncell, s));
+    k_hash_pass<<<eb, 256, 0, s>>>(h->bbox, E, g, 1, cnt, h->cell_off, h->cell_el);
+    FP_HIP_H(hipGetLastError());
+    FP_HIP_H(hipMemsetAsync(d_flag, 0, sizeof(int), s));
+    k_hash_sort<<<(int)((h->ncell + 255) / 256), 256, 0, s>>>(h->cell_off, h->cell_el,
+                                                              h->ncell, d_flag);
+    FP_HIP_H(hipGetLastError());
+    int maxlen = 0;
+    FP_HIP_H(hipMemcpyAsync(&maxlen, d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    FP_HIP_H(hipStreamSynchronize(s));
+    (void)hipFree(cnt);
+    (void)hipFree(d_flag);
+    h->max_cell = maxlen;
+    h->MC = std::max(1, maxlen);
+
+    // workspace
+    const size_t M = (size_t)max_points, MC = (size_t)h->MC;
+    if ((double)M * (double)MC >= 2147483647.0) {
+        release(h);
+        set_error("findpts_setup: max_points x longest cell list exceeds 2^31; lower max_points");
+        return FP_ERANGE;
+    }
+    FP_HIP_H(dalloc(h, &h->ncand, M));
+    FP_HIP_H(dalloc(h, &h->cand_el, M * MC));
+    FP_HIP_H(dalloc(h, &h->cand_pos, M * MC));
+    FP_HIP_H(dalloc(h, &h->elem_cnt, (size_t)E + 1));
+    FP_HIP_H(dalloc(h, &h->elem_off, (size_t)E + 1));
+    FP_HIP_H(dalloc(h, &h->order, M * MC));
+    FP_HIP_H(dalloc(h, &h->res, M * MC * 4));
+    FP_HIP_H(dalloc(h, &h->res_in, M * MC));
+    if (h->delta) FP_HIP_H(dalloc(h, &h->res_dl, M * MC));
+    FP_HIP_H(dalloc(h, &h->ev_cnt, (size_t)E + 1));
+    FP_HIP_H(dalloc(h, &h->ev_off, (size_t)E + 1));
+    FP_HIP_H(dalloc(h, &h->ev_pos, M));
+    FP_HIP_H(dalloc(h, &h->ev_order, M));
+    FP_HIP_H(hipStreamSynchronize(s));
+    *out = h;
+    return FP_OK;
+}
+
+extern "C" int findpts_free(fp_handle *h)
+{
+    if (!h) return FP_OK;
+    (void)hipDeviceSynchronize();
+    release(h);
+    return FP_OK;
+}
+
+extern "C" int findpts_set_precision(fp_handle *h, int precision)
+{
+    if (!h || (precision != FP_PREC_FP64 && precision != FP_PREC_MIXED)) {
+        set_error("findpts_set_precision: bad handle or precision");
+        return FP_EINVAL;
+    }
+    h->precision = precision;
+    return FP_OK;
+}
+
+extern "C" int findpts_stats(fp_handle *h, long long *h_counts, int reset)
+{
+    if (!h || !h_counts) {
+        set_error("findpts_stats: NULL argument");
+        return FP_EINVAL;
+    }
+    unsigned long long v[4];
+    FP_HIP(hipDeviceSynchronize());
+    FP_HIP(hipMemcpy(v, h->stats, sizeof v, hipMemcpyDeviceToHost));
+    for (int i = 0; i < 3; ++i) h_counts[i] = (long long)v[i];
+    if (reset) FP_HIP(hipMemset(h->stats, 0, sizeof v));
+    return FP_OK;
+}
+
+extern "C" int findpts_get_bbox(fp_handle *h, double *h_bbox, double *h_size)
+{
+    if (!h || !h_bbox || !h_size) {
+        set_error("findpts_get_bbox: NULL argument");
+        return FP_EINVAL;
+    }
+    FP_HIP(hipDeviceSynchronize());
+    FP_HIP(hipMemcpy(h_bbox, h->bbox, sizeof(double) * 6 * h->E, hipMemcpyDeviceToHost));
+    FP_HIP(hipMemcpy(h_size, h->esize, sizeof(double) * h->E, hipMemcpyDeviceToHost));
+    return FP_OK;
+}
+
+extern "C" int findpts_get_hash(fp_handle *h, int *h_nc, double *h_lo, double *h_dx,
+                                long long *h_meta)
+{
+    if (!h || !h_nc || !h_lo || !h_dx || !h_meta) {
+        set_error("findpts_get_hash: NULL argument");
+        return FP_EINVAL;
+    }
+    for (int a = 0; a < 3; ++a) {
+        h_nc[a] = h->grid.nc[a];
+        h_lo[a] = h->grid.lo[a];
+        h_dx[a] = 1.0 / h->grid.inv[a];
+    }
+    h_meta[0] = h->ncell;
+    h_meta[1] = h->nnz;
+    h_meta[2] = h->max_cell;
+    return FP_OK;
+}
+
+extern "C" int findpts_get_cells(fp_handle *h, int *h_cell_off, int *h_cell_el)
+{
+    if (!h || !h_cell_off || !h_cell_el) {
+        set_error("findpts_get_cells: NULL argument");
+        return FP_EINVAL;
+    }
+    FP_HIP(hipDeviceSynchronize());
+    FP_HIP(hipMemcpy(h_cell_off, h->cell_off, sizeof(int) * (h->ncell + 1),
+                     hipMemcpyDeviceToHost));
+    FP_HIP(hipMemcpy(h_cell_el, h->cell_el, sizeof(int) * (h->nnz ? h->nnz : 0),
+                     hipMemcpyDeviceToHost));
+    return FP_OK;
+}
+
+extern "C" int findpts_footprint(const fp_handle *h, size_t *h_bytes)
+{
+    if (!h || !h_bytes) {
+        set_error("findpts_footprint: NULL argument");
+        return FP_EINVAL;
+    }
+    *h_bytes = h->bytes;
+    return FP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Timing with events on the call's stream.
+// ---------------------------------------------------------------------------
+namespace fp {
+hipEvent_t pool_event(fp_handle *h)
+{
+    if (!h->event_pool.empty()) {
+        hipEvent_t e = h->event_pool.back();
+        h->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+}  // namespace fp
+
+extern "C" int findpts_timing(fp_handle *h, int enable)
+{
+    if (!h) {
+        set_error("findpts_timing: NULL handle");
+        return FP_EINVAL;
+    }
+    h->timing = enable != 0;
+    return FP_OK;
+}
+
+extern "C" int findpts_timing_read(fp_handle *h, double *h_ms, long long *h_n)
+{
+    if (!h || !h_ms || !h_n) {
+        set_error("findpts_timing_read: NULL argument");
+        return FP_EINVAL;
+    }
+    for (int i = 0; i < 4; ++i) {
+        h_ms[i] = 0.0;
+        h_n[i] = 0;
+    }
+    for (auto &t : h->timed) {
+        FP_HIP(hipEventSynchronize(t.b));
+        float ms = 0.0f;
+        FP_HIP(hipEventElapsedTime(&ms, t.a, t.b));
+        if (t.phase >= 0 && t.phase < 4) {
+            h_ms[t.phase] += ms;
+            h_n[t.phase] += 1;
+        }
+        h->event_pool.push_back(t.a);
+        h->event_pool.push_back(t.b);
+    }
+    h->timed.clear();
+    return FP_OK;
+}

@@ -1,0 +1,238 @@
+"""Thin ctypes binding of libfindpts.so (the gfx950 findpts library).
+
+Same names as the C ABI in include/findpts.h.  This module only marshals
+arguments (torch CUDA tensors -> device pointers, the current torch stream ->
+hipStream_t) and allocates output tensors when the caller does not pass
+them; every step of point location and interpolation runs in the library's
+HIP kernels.  There is no fallback: if the library is not built, or a tensor
+is not a contiguous CUDA tensor of the right dtype, a call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfindpts.so")
+
+FP_OK, FP_EINVAL, FP_ENOMEM, FP_EHIP, FP_ESTATE, FP_ERANGE, FP_EBUSY = 0, -1, -2, -3, -4, -5, -6
+FP_INSIDE, FP_BORDER, FP_NOT_FOUND = 0, 1, 2
+FP_PREC_FP64, FP_PREC_MIXED = 0, 1
+
+# Every symbol the C ABI exports (checked against include/findpts.h by tests).
+SYMBOLS = ("findpts_setup", "findpts", "findpts_eval", "findpts_set_precision",
+           "findpts_stats", "findpts_timing", "findpts_timing_read",
+           "findpts_get_bbox", "findpts_get_hash", "findpts_get_cells",
+           "findpts_footprint", "findpts_free", "fp_last_error", "fp_copy")
+
+
+class FindptsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libfindpts.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1811_04891_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, ip, dp, llp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_longlong)
+    L.findpts_setup.argtypes = [C.POINTER(vp), vp, vp, vp, C.c_int, C.c_int, C.c_double,
+                                vp, vp, C.c_int, C.c_int, vp]
+    L.findpts.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp]
+    L.findpts_eval.argtypes = [vp, C.c_int, vp, vp, vp, C.c_int, C.POINTER(vp), vp, vp]
+    L.findpts_set_precision.argtypes = [vp, C.c_int]
+    L.findpts_stats.argtypes = [vp, llp, C.c_int]
+    L.findpts_timing.argtypes = [vp, C.c_int]
+    L.findpts_timing_read.argtypes = [vp, dp, llp]
+    L.findpts_get_bbox.argtypes = [vp, dp, dp]
+    L.findpts_get_hash.argtypes = [vp, ip, dp, dp, llp]
+    L.findpts_get_cells.argtypes = [vp, ip, ip]
+    L.findpts_footprint.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.findpts_free.argtypes = [vp]
+    L.fp_last_error.restype = C.c_char_p
+    L.fp_last_error.argtypes = []
+    L.fp_copy.argtypes = [vp, vp, C.c_size_t, vp]
+    for name in SYMBOLS:
+        if name != "fp_last_error":
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int, what: str):
+    if rc != FP_OK:
+        raise FindptsError(rc, f"{what}: {lib().fp_last_error().decode()}")
+
+
+def _ptr(t: Optional[torch.Tensor], dtype, name: str, numel: Optional[int] = None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> C.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, torch.cuda.Stream):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+class Handle:
+    """Owns an fp_handle*; freed with findpts_free."""
+
+    def __init__(self, ptr: C.c_void_p, E: int, N: int, device: torch.device):
+        self.ptr, self.E, self.N, self.device = ptr, E, N, device
+        self.n1 = N + 1
+        self.V = self.n1 ** 3
+
+    def free(self):
+        if self.ptr is not None and self.ptr.value:
+            _check(lib().findpts_free(self.ptr), "findpts_free")
+        self.ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def findpts_setup(x: torch.Tensor, y: torch.Tensor, z: torch.Tensor, N: int,
+                  tol: float = 1e-12, elem_session: Optional[torch.Tensor] = None,
+                  delta: Optional[torch.Tensor] = None, max_points: int = 1 << 20,
+                  precision: int = FP_PREC_FP64, stream=None) -> Handle:
+    n1 = N + 1
+    V = n1 ** 3
+    if x.numel() % V:
+        raise ValueError("coordinate arrays must hold E*(N+1)^3 values")
+    E = x.numel() // V
+    h = C.c_void_p()
+    rc = lib().findpts_setup(C.byref(h), _ptr(x, torch.float64, "x", E * V),
+                             _ptr(y, torch.float64, "y", E * V),
+                             _ptr(z, torch.float64, "z", E * V), E, N, float(tol),
+                             _ptr(elem_session, torch.int32, "elem_session", E),
+                             _ptr(delta, torch.float64, "delta", E * V),
+                             int(max_points), int(precision), _stream(stream))
+    _check(rc, "findpts_setup")
+    return Handle(h, E, N, x.device)
+
+
+def findpts(h: Handle, pts: torch.Tensor, pt_session: Optional[torch.Tensor] = None,
+            code=None, el=None, rst=None, dist2=None, stream=None):
+    """Locate pts (npts x 3, float64).  Returns (code, el, rst, dist2)."""
+    n = pts.numel() // 3
+    dev = pts.device
+    code = torch.empty(n, dtype=torch.int32, device=dev) if code is None else code
+    el = torch.empty(n, dtype=torch.int32, device=dev) if el is None else el
+    rst = torch.empty((n, 3), dtype=torch.float64, device=dev) if rst is None else rst
+    dist2 = torch.empty(n, dtype=torch.float64, device=dev) if dist2 is None else dist2
+    rc = lib().findpts(h.ptr, n, _ptr(pts, torch.float64, "pts", 3 * n),
+                       _ptr(pt_session, torch.int32, "pt_session", n),
+                       _ptr(code, torch.int32, "code", n), _ptr(el, torch.int32, "el", n),
+                       _ptr(rst, torch.float64, "rst", 3 * n),
+                       _ptr(dist2, torch.float64, "dist2", n), _stream(stream))
+    _check(rc, "findpts")
+    return code, el, rst, dist2
+
+
+def findpts_eval(h: Handle, code: torch.Tensor, el: torch.Tensor, rst: torch.Tensor,
+                 fields: Sequence[torch.Tensor], out: Optional[torch.Tensor] = None,
+                 stream=None) -> torch.Tensor:
+    """Interpolate fields (each E*(N+1)^3 float64) at located points.
+    Returns out (nfields x npts)."""
+    n = code.numel()
+    nf = len(fields)
+    if out is None:
+        out = torch.empty((nf, n), dtype=torch.float64, device=code.device)
+    arr = (C.c_void_p * max(nf, 1))(*[_ptr(f, torch.float64, f"fields[{i}]", h.E * h.V)
+                                       for i, f in enumerate(fields)])
+    rc = lib().findpts_eval(h.ptr, n, _ptr(code, torch.int32, "code", n),
+                            _ptr(el, torch.int32, "el", n),
+                            _ptr(rst, torch.float64, "rst", 3 * n), nf, arr,
+                            _ptr(out, torch.float64, "out", nf * n), _stream(stream))
+    _check(rc, "findpts_eval")
+    return out
+
+
+def findpts_set_precision(h: Handle, precision: int):
+    _check(lib().findpts_set_precision(h.ptr, int(precision)), "findpts_set_precision")
+
+
+def findpts_stats(h: Handle, reset: bool = False):
+    """(pairs examined, Newton iterations, points located) since setup/reset."""
+    v = (C.c_longlong * 3)()
+    _check(lib().findpts_stats(h.ptr, v, int(bool(reset))), "findpts_stats")
+    return tuple(v)
+
+
+def findpts_timing(h: Handle, enable: bool = True):
+    _check(lib().findpts_timing(h.ptr, int(bool(enable))), "findpts_timing")
+
+
+def findpts_timing_read(h: Handle):
+    """{phase: (total ms, launches)} for locate kernel, eval kernel, findpts, findpts_eval."""
+    ms, n = (C.c_double * 4)(), (C.c_longlong * 4)()
+    _check(lib().findpts_timing_read(h.ptr, ms, n), "findpts_timing_read")
+    names = ("locate_kernel", "eval_kernel", "findpts", "findpts_eval")
+    return {names[i]: (ms[i], n[i]) for i in range(4)}
+
+
+def findpts_get_bbox(h: Handle):
+    import numpy as np
+    b, s = np.zeros(6 * h.E), np.zeros(h.E)
+    _check(lib().findpts_get_bbox(h.ptr, b.ctypes.data_as(C.POINTER(C.c_double)),
+                                  s.ctypes.data_as(C.POINTER(C.c_double))), "findpts_get_bbox")
+    return b.reshape(h.E, 6), s
+
+
+def findpts_get_hash(h: Handle):
+    import numpy as np
+    nc, lo, dx, meta = (C.c_int * 3)(), np.zeros(3), np.zeros(3), (C.c_longlong * 3)()
+    _check(lib().findpts_get_hash(h.ptr, nc, lo.ctypes.data_as(C.POINTER(C.c_double)),
+                                  dx.ctypes.data_as(C.POINTER(C.c_double)), meta),
+           "findpts_get_hash")
+    return list(nc), lo, dx, tuple(meta)
+
+
+def findpts_get_cells(h: Handle):
+    import numpy as np
+    _, _, _, (ncell, nnz, _) = findpts_get_hash(h)
+    off, cel = np.zeros(ncell + 1, np.int32), np.zeros(max(nnz, 1), np.int32)
+    _check(lib().findpts_get_cells(h.ptr, off.ctypes.data_as(C.POINTER(C.c_int)),
+                                   cel.ctypes.data_as(C.POINTER(C.c_int))), "findpts_get_cells")
+    return off, cel[:nnz]
+
+
+def findpts_footprint(h: Handle) -> int:
+    v = C.c_size_t()
+    _check(lib().findpts_footprint(h.ptr, C.byref(v)), "findpts_footprint")
+    return v.value
+
+
+def fp_copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst too small")
+    _check(lib().fp_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                         nbytes, _stream(stream)), "fp_copy")

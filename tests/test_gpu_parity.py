@@ -1,0 +1,294 @@
+"""GPU parity: the HIP findpts / findpts_eval path (through the C ABI)
+against the CPU oracle on the same seeded inputs.  Sizes span many element
+wavefronts and ragged tails; the full 1.01M-point annulus workload is run in
+the same launch configuration as the benchmark and checked on a sample."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as w
+from parity import compare_eval, compare_locate
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _fp():
+    from paper_1811_04891_amd import findpts as fp
+    return fp
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda:0")
+
+
+def _run(fp, mesh, pts, dev, max_points=1 << 16, psess=None, fields=(), tol=TOL):
+    md = mesh.to(dev)
+    h = fp.findpts_setup(md.x, md.y, md.z, mesh.N, tol=tol, elem_session=md.session,
+                         delta=md.delta, max_points=max_points)
+    ps = None if psess is None else psess.to(dev)
+    code, el, rst, d2 = fp.findpts(h, pts.to(dev), ps)
+    out = None
+    if fields:
+        out = fp.findpts_eval(h, code, el, rst, [f.to(dev) for f in fields])
+    torch.cuda.synchronize()
+    res = (code.cpu().numpy(), el.cpu().numpy(), rst.cpu().numpy(), d2.cpu().numpy())
+    return h, res, (None if out is None else out.cpu().numpy())
+
+
+def test_c1_unit_cube_full(dev):
+    fp = _fp()
+    _say("case: unit cube N=5, 1e4 points, 1 field")
+    mesh = w.cube_c1()
+    pts = w.queries_c1()
+    X = mesh.x
+    f = X ** 2 + mesh.y * mesh.z + mesh.z ** 3
+    h, g, out = _run(fp, mesh, pts, dev, fields=[f])
+    om = oracle.OracleMesh.from_mesh(mesh, TOL)
+    o = om.findpts(pts.numpy())
+    _, hs = om.bbox()
+    st = compare_locate(om, pts.numpy(), g, o, hs, TOL)
+    assert st["inside"] == len(pts)
+    ref = om.eval(g[0], g[1], g[2], [f.numpy()])
+    compare_eval(out, ref, [f.numpy()])
+    # pairs examined = oracle candidate count (integer work, exact)
+    pairs, iters, npts = fp.findpts_stats(h)
+    assert pairs == om.last_stats[0] and npts == len(pts)
+    _say(f"c1 ok {st}, gpu newton iters/pair {iters / pairs:.2f} oracle {om.last_stats[1] / om.last_stats[0]:.2f}")
+
+
+def test_setup_boxes_and_hash(dev):
+    fp = _fp()
+    for mesh in (w.cube_c1(), w.annulus_mesh(4, 16, 3, N=7)):
+        _say(f"case: setup parity {mesh.name} E={mesh.E}")
+        md = mesh.to(dev)
+        h = fp.findpts_setup(md.x, md.y, md.z, mesh.N, max_points=16)
+        gb, gh = fp.findpts_get_bbox(h)
+        om = oracle.OracleMesh.from_mesh(mesh)
+        ob, oh = om.bbox()
+        assert np.array_equal(gh, oh)  # node extents: exact min/max
+        scale = np.max(np.abs(ob))
+        assert np.max(np.abs(gb - ob)) <= 1e-14 * scale
+        nc, lo, dx, (ncell, nnz, maxc) = fp.findpts_get_hash(h)
+        off, cel = fp.findpts_get_cells(h)
+        assert ncell == nc[0] * nc[1] * nc[2] and off[-1] == nnz
+        # every cell list = ascending ids of boxes overlapping the cell, computed
+        # on the host from the GPU's own boxes and grid
+        inv = 1.0 / dx
+        def cidx(v, a):
+            return np.clip(np.floor((v - lo[a]) * inv[a]).astype(int), 0, nc[a] - 1)
+        ref = [[] for _ in range(ncell)]
+        for e in range(mesh.E):
+            r = [(cidx(gb[e, 2 * a], a), cidx(gb[e, 2 * a + 1], a)) for a in range(3)]
+            for k in range(r[2][0], r[2][1] + 1):
+                for j in range(r[1][0], r[1][1] + 1):
+                    for i in range(r[0][0], r[0][1] + 1):
+                        ref[i + nc[0] * (j + nc[1] * k)].append(e)
+        for c in range(ncell):
+            assert list(cel[off[c]:off[c + 1]]) == ref[c]
+        assert maxc == max(len(r) for r in ref)
+        h.free()
+
+
+@pytest.fixture(scope="module")
+def c2(dev):
+    mesh = w.annulus_c2()
+    pts = w.queries_c2()
+    om = oracle.OracleMesh.from_mesh(mesh, TOL)
+    return mesh, pts, om
+
+
+def test_c2_annulus_subset(dev, c2):
+    fp = _fp()
+    mesh, pts, om = c2
+    sub = pts[:60_001]  # ragged
+    _say("case: annulus C2 mesh, 60001-point subset")
+    fields, _ = w.poly_fields(mesh, 2, seed=2)
+    h, g, out = _run(fp, mesh, sub, dev, max_points=1 << 17, fields=fields)
+    o = om.findpts(sub.numpy())
+    _, hs = om.bbox()
+    st = compare_locate(om, sub.numpy(), g, o, hs, TOL, check_residual_every=7)
+    assert st["border"] > 0 and st["notfound"] > 0
+    ref = om.eval(g[0], g[1], g[2], [f.numpy() for f in fields])
+    compare_eval(out, ref, [f.numpy() for f in fields])
+    pairs, _, _ = fp.findpts_stats(h)
+    assert pairs == om.last_stats[0]
+    _say(f"c2 subset ok {st}")
+
+
+def test_c2_full_size_sampled(dev, c2):
+    """The benchmark workload (1.01M points, one pass of max_points = 2^20),
+    checked on a seeded sample of 20,000 outputs."""
+    fp = _fp()
+    mesh, pts, om = c2
+    _say("case: annulus C2 full 1.01M points, sampled parity")
+    h, g, _ = _run(fp, mesh, pts, dev, max_points=1 << 20)
+    rng = np.random.default_rng(22)
+    idx = np.sort(rng.choice(len(pts), 20_000, replace=False))
+    o = om.findpts(pts.numpy()[idx])
+    gs = tuple(a[idx] for a in g)
+    _, hs = om.bbox()
+    st = compare_locate(om, pts.numpy()[idx], gs, o, hs, TOL, check_residual_every=5)
+    # whole-output properties at full size
+    gc, ge, gr, gd = g
+    assert np.all((gc >= 0) & (gc <= 2))
+    assert np.all((ge >= -1) & (ge < mesh.E))
+    assert np.all(np.abs(gr) <= 1.0)
+    assert np.all((gc == 2) == np.isinf(gd))
+    assert np.sum(gc == 0) > 0.985 * len(pts)
+    _say(f"c2 full sampled ok {st}")
+
+
+def test_chunked_equals_single_pass(dev):
+    fp = _fp()
+    mesh = w.annulus_mesh(4, 16, 3, N=5)
+    pts = w.queries_c2(n_in=20_000, seed=9)
+    _say("case: multi-pass (max_points=4099) vs single pass")
+    _, g1, _ = _run(fp, mesh, pts, dev, max_points=1 << 16)
+    _, g2, _ = _run(fp, mesh, pts, dev, max_points=4099)
+    for a, b in zip(g1, g2):
+        assert np.array_equal(a, b)
+
+
+def test_edge_cases(dev):
+    fp = _fp()
+    mesh = w.cube_c1()
+    md = mesh.to(dev)
+    h = fp.findpts_setup(md.x, md.y, md.z, mesh.N, max_points=256)
+    _say("case: edge cases (empty, NaN, far, ragged sizes)")
+    e = torch.empty((0, 3), dtype=torch.float64, device=dev)
+    code, el, rst, d2 = fp.findpts(h, e)
+    assert code.numel() == 0
+    odd = torch.tensor([[np.nan, 0.5, 0.5], [0.5, np.inf, 0.5], [5.0, 0.5, 0.5],
+                        [0.5, 0.5, -1e9], [0.0, 0.0, 0.0], [1.0, 1.0, 1.0]],
+                       dtype=torch.float64, device=dev)
+    code, el, rst, d2 = fp.findpts(h, odd)
+    c = code.cpu().numpy()
+    assert list(c[:4]) == [2, 2, 2, 2] and list(c[4:]) == [0, 0]
+    assert list(el.cpu().numpy()[:4]) == [-1] * 4
+    assert np.all(np.isinf(d2.cpu().numpy()[:4]))
+    vals = fp.findpts_eval(h, code, el, rst, [md.x])
+    v = vals.cpu().numpy()[0]
+    assert np.all(np.isnan(v[:4])) and abs(v[4]) <= 1e-15 and abs(v[5] - 1.0) <= 1e-15
+    om = oracle.OracleMesh.from_mesh(mesh)
+    _, hs = om.bbox()
+    for n in (1, 63, 64, 65, 255, 256, 257, 1000):
+        pts = w.queries_c1(n, seed=100 + n)
+        code, el, rst, d2 = fp.findpts(h, pts.to(dev))
+        g = (code.cpu().numpy(), el.cpu().numpy(), rst.cpu().numpy(), d2.cpu().numpy())
+        compare_locate(om, pts.numpy(), g, om.findpts(pts.numpy()), hs, TOL)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 9, 10, 11, 15])
+def test_orders(dev, N):
+    fp = _fp()
+    _say(f"case: order N={N}")
+    mesh = w.annulus_mesh(2, 8, 2, N=N) if N >= 3 else w.cube_c1(perturb=0.0)
+    if N < 3:
+        mesh = w.box_mesh(3, 3, 2, lo=(-1, 0, 0), hi=(2, 1, 0.5), N=N)
+    rng = np.random.default_rng(N)
+    if N >= 3:
+        rho = np.sqrt(rng.uniform(0.2, 1.2, 3000))
+        th = rng.uniform(0, 2 * np.pi, 3000)
+        pts = np.stack([rho * np.cos(th), rho * np.sin(th), rng.uniform(-0.05, 1.05, 3000)], 1)
+    else:
+        pts = rng.uniform((-1.1, -0.1, -0.1), (2.1, 1.1, 0.6), (3000, 3))
+    pts = torch.as_tensor(pts)
+    fields, _ = w.ref_poly_fields(mesh, 1, seed=N)
+    h, g, out = _run(fp, mesh, pts, dev, fields=fields)
+    om = oracle.OracleMesh.from_mesh(mesh, TOL)
+    o = om.findpts(pts.numpy())
+    _, hs = om.bbox()
+    compare_locate(om, pts.numpy(), g, o, hs, TOL)
+    ref = om.eval(g[0], g[1], g[2], [fields[0].numpy()])
+    compare_eval(out, ref, [fields[0].numpy()], rel=1e-12)
+
+
+def test_exact_recovery(dev):
+    fp = _fp()
+    _say("case: exact recovery through the analytic polynomial map")
+    from helpers import box_affine, box_elem_ids, phi_np
+    n = (3, 3, 3)
+    mesh, _ = w.poly_map_mesh(*n, N=4, amp=0.04)
+    ex, ey, ez = box_elem_ids(mesh.E, n)
+    rng = np.random.default_rng(31)
+    P = 5000
+    et = rng.integers(0, mesh.E, P)
+    rt = rng.uniform(-1, 1, (P, 3))
+    a = np.array([box_affine(ex[e], ey[e], ez[e], n, (0, 0, 0), (1, 1, 1), r) for e, r in zip(et, rt)])
+    pts = np.stack(phi_np(a[:, 0], a[:, 1], a[:, 2], amp=0.04), 1)
+    h, g, _ = _run(fp, mesh, torch.as_tensor(pts), dev)
+    gc, ge, gr, gd = g
+    assert np.all(gc == 0)
+    same = ge == et
+    assert np.max(np.abs(gr[same] - rt[same])) <= 1e-11
+    assert np.all(np.min(1 - np.abs(rt[~same]), axis=1) <= 1e-10)
+
+
+def test_eval_reference_polynomials(dev):
+    fp = _fp()
+    _say("case: eval of reference-space polynomials, 3 fields, random (e, r)")
+    mesh = w.annulus_mesh(3, 8, 2, N=7)
+    fields, coef = w.ref_poly_fields(mesh, 3, seed=4)
+    md = mesh.to(dev)
+    h = fp.findpts_setup(md.x, md.y, md.z, mesh.N, max_points=5000)
+    rng = np.random.default_rng(4)
+    P = 4001
+    el = torch.as_tensor(rng.integers(0, mesh.E, P).astype(np.int32))
+    rst = torch.as_tensor(rng.uniform(-1, 1, (P, 3)))
+    code = torch.zeros(P, dtype=torch.int32)
+    out = fp.findpts_eval(h, code.to(dev), el.to(dev), rst.to(dev), [f.to(dev) for f in fields])
+    out = out.cpu().numpy()
+    a = np.arange(8)
+    for f in range(3):
+        for p in range(0, P, 13):
+            c = coef[f, el[p]]
+            r = rst[p].numpy()
+            ref = np.einsum("cba,c,b,a->", c, r[2] ** a, r[1] ** a, r[0] ** a)
+            assert abs(out[f, p] - ref) <= 1e-13 * np.abs(c).sum()
+
+
+def test_three_sessions_delta(dev):
+    fp = _fp()
+    _say("case: three sessions with distance discriminator")
+    boxes = [((0, 0, 0), (3, 1, 1)), ((0, 0, 0), (2, 1, 1)), ((1, 0, 0), (3, 1, 1))]
+    ms = [w.box_mesh(1, 1, 1, lo, hi, N=2) for lo, hi in boxes]
+    x = torch.cat([m.x for m in ms]); y = torch.cat([m.y for m in ms]); z = torch.cat([m.z for m in ms])
+    delta = torch.cat([torch.full_like(ms[0].x, 100.0), 2.0 - ms[1].x, ms[2].x - 1.0])
+    mesh = w.Mesh("three", 2, x, y, z, torch.tensor([0, 1, 2], dtype=torch.int32), delta)
+    xs = np.array([0.5, 1.2, 1.4, 1.5, 1.6, 1.9, 2.5])
+    pts = torch.as_tensor(np.stack([xs, np.full_like(xs, 0.3), np.full_like(xs, 0.7)], 1))
+    for tag, ref in ((0, [1, 1, 1, 1, 2, 2, 2]), (1, [0] * 7), (-1, [0] * 7)):
+        ps = torch.full((7,), tag, dtype=torch.int32)
+        _, g, _ = _run(fp, mesh, pts, dev, psess=ps)
+        assert list(g[0]) == [0] * 7 and list(g[1]) == ref, (tag, g[1])
+
+
+def test_two_sessions_overlap_subset(dev):
+    fp = _fp()
+    _say("case: two overlapping sessions (box with hole + annulus), interface nodes")
+    mesh = w.overlap_c3()
+    pts, tags = w.c3_interface_nodes(mesh)
+    rng = np.random.default_rng(3)
+    idx = torch.as_tensor(np.sort(rng.choice(len(pts), 30_000, replace=False)))
+    pts, tags = pts[idx].contiguous(), tags[idx].contiguous()
+    h, g, _ = _run(fp, mesh, pts, dev, psess=tags)
+    om = oracle.OracleMesh.from_mesh(mesh, TOL)
+    o = om.findpts(pts.numpy(), tags.numpy())
+    _, hs = om.bbox()
+    st = compare_locate(om, pts.numpy(), g, o, hs, TOL, check_residual_every=3)
+    sess = mesh.session.numpy()
+    found = g[0] != 2
+    assert np.all(sess[g[1][found]] != tags.numpy()[found])
+    _say(f"two sessions ok {st}")
