@@ -78,8 +78,10 @@ def test_setup_boxes_and_hash(dev):
         om = oracle.OracleMesh.from_mesh(mesh)
         ob, oh = om.bbox()
         assert np.array_equal(gh, oh)  # node extents: exact min/max
+        # the two sides sum the Bernstein transform in different orders (and
+        # the GPU fuses multiply-adds): a few ulps, far below the 1e-8 h margin
         scale = np.max(np.abs(ob))
-        assert np.max(np.abs(gb - ob)) <= 1e-14 * scale
+        assert np.max(np.abs(gb - ob)) <= 1e-13 * scale
         nc, lo, dx, (ncell, nnz, maxc) = fp.findpts_get_hash(h)
         off, cel = fp.findpts_get_cells(h)
         assert ncell == nc[0] * nc[1] * nc[2] and off[-1] == nnz
