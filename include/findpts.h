@@ -135,9 +135,13 @@ FP_API int findpts_set_precision(fp_handle *h, int precision);
 
 /*
  * findpts_stats -- cumulative counters since setup (or the last reset),
- * written to host memory: h_counts[0] = (point, candidate element) pairs
- * examined, h_counts[1] = Newton iterations, h_counts[2] = points located.
- * Synchronises the device.  reset != 0 zeroes them afterwards.
+ * written to host memory (4 values): h_counts[0] = (point, element) pairs
+ * solved by Newton, h_counts[1] = Newton iterations, h_counts[2] = points
+ * located, h_counts[3] = candidates of the method (hash cell + axis-aligned
+ * element box + session test; the library solves only those whose oriented
+ * box also holds the point, then redoes points left without an inside
+ * element with all of them).  Synchronises the device.  reset != 0 zeroes
+ * them afterwards.
  */
 FP_API int findpts_stats(fp_handle *h, long long *h_counts, int reset);
 

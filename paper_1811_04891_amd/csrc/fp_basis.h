@@ -87,16 +87,21 @@ struct Unroll {
     static constexpr int jk = (N1 <= 10) ? N1 : 1;
 };
 
+// Element data staged in LDS, read through the LDS address space.
+template <class T>
+using lptr = const __attribute__((address_space(3))) T *;
+
 // Software-pipelined walk over the node rows of an element, expanded at
 // compile time.  Item n is the row (j, k) = (n / C % N1, n / (C N1)) of
 // array c = n % C (C = 3 coordinates, or 1 field), N1 values along r.  Rows
-// are loaded kPrefetch items ahead into scalar registers; scheduling fences
-// keep the compiler from hoisting every load to the top (which overflows the
-// scalar register file).
+// are loaded kPrefetch items ahead (into scalar registers from the scalar
+// cache, or into vector registers from LDS); scheduling fences keep the
+// compiler from hoisting every load to the top, which would overflow the
+// register file.
 constexpr int kPrefetch = 2;
 
-template <int N1, int C, int n, class T, class Acc>
-__device__ __forceinline__ void walk_rows(cptr<T> X, T (&buf)[kPrefetch + 1][N1], Acc &acc)
+template <int N1, int C, int n, class P, class T, class Acc>
+__device__ __forceinline__ void walk_rows(P X, T (&buf)[kPrefetch + 1][N1], Acc &acc)
 {
     constexpr int V = N1 * N1 * N1;
     constexpr int NI = C * N1 * N1;
@@ -159,6 +164,32 @@ struct GeoAcc {
         }
     }
 };
+
+// Geometry and Jacobian with the element block in LDS (per-lane base: lanes
+// of one wavefront may work on different elements of a staged group).
+template <int N1, class T>
+__device__ __forceinline__ void geo_eval_lds(lptr<T> X, BasisPtr<T> B, const T (&r)[3],
+                                             T (&x)[3], T (&J)[9])
+{
+    static_assert(N1 <= 10, "LDS path is unrolled");
+    GeoAcc<N1, T> A;
+    lagrange_d<N1>(B, r[0], A.hr, A.dr);
+    lagrange_d<N1>(B, r[1], A.hs, A.ds);
+    lagrange_d<N1>(B, r[2], A.ht, A.dt);
+    T buf[kPrefetch + 1][N1];
+    walk_rows<N1, 3, 0>(X, buf, A);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        x[c] = A.v[c];
+        J[3 * c + 0] = A.vr[c];
+        J[3 * c + 1] = A.vs[c];
+        J[3 * c + 2] = A.vt[c];
+        FP_KEEP(x[c]);
+        FP_KEEP(J[3 * c + 0]);
+        FP_KEEP(J[3 * c + 1]);
+        FP_KEEP(J[3 * c + 2]);
+    }
+}
 
 // x_c(r) and J[c][d] = dx_c/dr_d for the three coordinates of one element,
 // X = element block (3 x V, r index fastest), sum-factorised: contraction
@@ -256,6 +287,29 @@ __device__ __forceinline__ void geo_value(cptr<T> X, BasisPtr<T> B,
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) x[c] = v[c];
+}
+
+// Scalar field value at r with lane-varying element data (vector loads).
+template <int N1>
+__device__ __forceinline__ double field_value_v(const double *__restrict__ F,
+                                                const double (&hr)[N1], const double (&hs)[N1],
+                                                const double (&ht)[N1])
+{
+    double v = 0.0;
+#pragma unroll 1
+    for (int k = 0; k < N1; ++k) {
+        double cs = 0.0;
+#pragma unroll 1
+        for (int j = 0; j < N1; ++j) {
+            double a = 0.0;
+            const double *row = F + N1 * (j + N1 * k);
+#pragma unroll
+            for (int i = 0; i < N1; ++i) a = fma(row[i], hr[i], a);
+            cs = fma(a, hs[j], cs);
+        }
+        v = fma(cs, ht[k], v);
+    }
+    return v;
 }
 
 // Scalar field value at r given the basis values.

@@ -81,9 +81,89 @@ __global__ __launch_bounds__(kWave) void k_eval(EvArgs a, FieldPtrs F, const dou
     }
 }
 
+// Field rows of one staged element: value-only contraction, r then s then t.
+template <int N1>
+struct FieldAcc {
+    double hr[N1], hs[N1], ht[N1];
+    double v, cs;
+    template <int c, int j, int k>
+    __device__ __forceinline__ void step(const double (&row)[N1])
+    {
+        double a = 0.0;
+#pragma unroll
+        for (int i = 0; i < N1; ++i) a = fma(row[i], hr[i], a);
+        cs = (j == 0) ? a * hs[0] : fma(a, hs[j], cs);
+        if constexpr (j == N1 - 1) v = (k == 0) ? cs * ht[0] : fma(cs, ht[k], v);
+    }
+};
+
+// Element groups staged in LDS, one field at a time.  A 256-thread block
+// owns G consecutive elements and all their points (contiguous in the
+// element-grouped order); for each field it stages the G element blocks
+// (padded by 16 bytes so lanes on different elements use different LDS
+// banks) and every thread interpolates its points.
+constexpr int kEvThreads = 256;
+
+template <int N1>
+struct EvGroup {
+    static constexpr int V = N1 * N1 * N1;
+    static constexpr int stride = V + 2;
+    static constexpr int G0 = (6 * 8192) / (stride * 8);
+    static constexpr int G = G0 < 1 ? 1 : (G0 > 32 ? 32 : G0);
+};
+
+template <int N1>
+__global__ __launch_bounds__(kEvThreads) void k_eval_grp(EvArgs a, FieldPtrs F,
+                                                         const double *__restrict__ basis)
+{
+    using Gr = EvGroup<N1>;
+    constexpr int V = Gr::V, G = Gr::G, S = Gr::stride;
+    __shared__ double sF[G * S];
+    const BasisPtr<double> B{as_const(basis)};
+    const int e0 = blockIdx.x * G;
+    const int ne = min(G, a.E - e0);
+    const int pb = a.off[e0], pe = a.off[e0 + ne];
+    if (pe <= pb) return;  // uniform across the block
+    for (int f = 0; f < a.nf; ++f) {
+        const double *src = F.f[f] + (long long)e0 * V;
+        for (int q = threadIdx.x; q < ne * V; q += kEvThreads) {
+            const int g = q / V;
+            sF[g * S + (q - g * V)] = src[q];
+        }
+        __syncthreads();
+        for (int u = pb + threadIdx.x; u < pe; u += kEvThreads) {
+            const int p = a.order[u];
+            const int g = a.el[p] - e0;
+            FieldAcc<N1> acc;
+            lagrange<N1>(B, a.rst[3 * (long long)p], acc.hr);
+            lagrange<N1>(B, a.rst[3 * (long long)p + 1], acc.hs);
+            lagrange<N1>(B, a.rst[3 * (long long)p + 2], acc.ht);
+            double buf[kPrefetch + 1][N1];
+            walk_rows<N1, 1, 0>((lptr<double>)(sF + g * S), buf, acc);
+            a.out[f * a.ostride + p] = acc.v;
+        }
+        __syncthreads();
+    }
+}
+
 static hipError_t launch_eval_kernel(int n1, int E, const EvArgs &a, const FieldPtrs &F,
                                      const double *B, hipStream_t s)
 {
+#define FP_LAUNCH_GRP(N1) \
+    k_eval_grp<N1><<<(E + EvGroup<N1>::G - 1) / EvGroup<N1>::G, kEvThreads, 0, s>>>(a, F, B)
+    switch (n1) {
+        case 2: FP_LAUNCH_GRP(2); return hipGetLastError();
+        case 3: FP_LAUNCH_GRP(3); return hipGetLastError();
+        case 4: FP_LAUNCH_GRP(4); return hipGetLastError();
+        case 5: FP_LAUNCH_GRP(5); return hipGetLastError();
+        case 6: FP_LAUNCH_GRP(6); return hipGetLastError();
+        case 7: FP_LAUNCH_GRP(7); return hipGetLastError();
+        case 8: FP_LAUNCH_GRP(8); return hipGetLastError();
+        case 9: FP_LAUNCH_GRP(9); return hipGetLastError();
+        case 10: FP_LAUNCH_GRP(10); return hipGetLastError();
+        default: break;
+    }
+#undef FP_LAUNCH_GRP
 #define FP_LAUNCH_EVAL(N1) k_eval<N1><<<E, kWave, 0, s>>>(a, F, B)
     switch (n1) {
         case 2: FP_LAUNCH_EVAL(2); break;

@@ -56,6 +56,8 @@ struct fp_handle {
     float *geom32 = nullptr;   // binary32 copy (mixed precision)
     double *esize = nullptr;   // E: h_e
     double *bbox = nullptr;    // E x 6
+    double *obb = nullptr;     // E x 18: frame Q (9, row-major, rows = axes),
+                               // centre (3), rotated lo (3), rotated hi (3)
     int *esess = nullptr;      // E or null
     double *delta = nullptr;   // E x V or null
 
@@ -77,6 +79,8 @@ struct fp_handle {
     double *res = nullptr;     // M x MC x 4: r, s, t, d2
     double *res_dl = nullptr;  // M x MC: delta at the candidate (if delta)
     int *res_in = nullptr;     // M x MC: inside flag
+    int *redo = nullptr;       // M: points without an inside candidate
+    int *redo_n = nullptr;     // 1: their count
     int *scan_tmp = nullptr;   // block sums of the device scan
     int scan_tmp_n = 0;
 
@@ -86,7 +90,9 @@ struct fp_handle {
     int *ev_pos = nullptr;     // M
     int *ev_order = nullptr;   // M
 
-    unsigned long long *stats = nullptr;  // [pairs, newton iterations, points]
+    // [pairs solved, Newton iterations, points located, axis-aligned box
+    //  candidates (the hash + box candidate count of the method)]
+    unsigned long long *stats = nullptr;
 
     fp::Basis basis{};
     fp::Basis32 basis32{};

@@ -25,6 +25,11 @@ struct LocArgs {
     const double *geom;
     const double *esize;
     const double *bbox;
+    const double *obb;   // non-null: also test the oriented box (first pass)
+    const int *idx;      // non-null: task t is point idx[t] (second pass)
+    const int *dcount;   // non-null: number of tasks, read on the device
+    int *redo;           // first pass: points without an inside candidate
+    int *redo_n;
     const double *delta;
     const int *esess;
     const int *cell_off;
@@ -33,7 +38,7 @@ struct LocArgs {
     const double *pts;
     const int *psess;
     int npts;
-    int MC;
+    int M;  // candidate slots are candidate-major: slot(t, k) = k * M + t
     double tol;
     int *ncand;
     int *cand_el;
@@ -54,47 +59,91 @@ __device__ __forceinline__ int cell_of(const Grid &g, int a, double x)
     return i < 0 ? 0 : (i >= g.nc[a] ? g.nc[a] - 1 : i);
 }
 
+__device__ __forceinline__ int task_count(const LocArgs &a)
+{
+    return a.dcount ? *a.dcount : a.npts;
+}
+
+// ncand[t] = candidate count | (1 << kFullBit) when the list is the method's
+// whole candidate set (no second pass needed for that point)
+constexpr int kFullBit = 30;
+constexpr int kCountMask = (1 << kFullBit) - 1;
+
+// Candidates of one point: hash cell, then the closed axis-aligned box and
+// the session exclusion (the method's candidate set), then, in the first
+// pass, the oriented box.  The oriented box holds the whole element, so it
+// never drops an element that contains the point; points left without an
+// inside candidate are redone with the axis-aligned set alone.
 __global__ __launch_bounds__(256) void k_cand(LocArgs a)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.npts) return;
-    const double x0 = a.pts[3 * (long long)p], x1 = a.pts[3 * (long long)p + 1],
-                 x2 = a.pts[3 * (long long)p + 2];
-    const int ps = a.psess ? a.psess[p] : -1;
-    int n = 0;
-    const Grid &g = a.g;
-    // NaN fails every comparison, so non-finite points find nothing
-    if (x0 >= g.lo[0] && x0 <= g.hi[0] && x1 >= g.lo[1] && x1 <= g.hi[1] && x2 >= g.lo[2] &&
-        x2 <= g.hi[2]) {
-        const long long c = cell_of(g, 0, x0) +
-                            (long long)g.nc[0] * (cell_of(g, 1, x1) +
-                                                  (long long)g.nc[1] * cell_of(g, 2, x2));
-        const int qb = a.cell_off[c], qe = a.cell_off[c + 1];
-        int *ce = a.cand_el + (long long)p * a.MC;
-        int *cp = a.cand_pos + (long long)p * a.MC;
-        for (int q = qb; q < qe; ++q) {
-            const int e = a.cell_el[q];
-            const double *b = a.bbox + 6 * (long long)e;
-            if (x0 < b[0] || x0 > b[1] || x1 < b[2] || x1 > b[3] || x2 < b[4] || x2 > b[5])
-                continue;
-            if (ps >= 0 && a.esess && a.esess[e] == ps) continue;
-            ce[n] = e;
-            cp[n] = atomicAdd(&a.elem_cnt[e], 1);
-            ++n;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int naabb = 0;
+    if (t < task_count(a)) {
+        const int p = a.idx ? a.idx[t] : t;
+        const double x0 = a.pts[3 * (long long)p], x1 = a.pts[3 * (long long)p + 1],
+                     x2 = a.pts[3 * (long long)p + 2];
+        const int ps = a.psess ? a.psess[p] : -1;
+        int n = 0, full = a.obb ? 0 : 1;
+        const Grid &g = a.g;
+        // NaN fails every comparison, so non-finite points find nothing
+        if (x0 >= g.lo[0] && x0 <= g.hi[0] && x1 >= g.lo[1] && x1 <= g.hi[1] &&
+            x2 >= g.lo[2] && x2 <= g.hi[2]) {
+            const long long c = cell_of(g, 0, x0) +
+                                (long long)g.nc[0] * (cell_of(g, 1, x1) +
+                                                      (long long)g.nc[1] * cell_of(g, 2, x2));
+            const int qb = a.cell_off[c], qe = a.cell_off[c + 1];
+            int *ce = a.cand_el + t;
+            int *cp = a.cand_pos + t;
+            // pass 0: oriented-box filter (first pass only); pass 1: every
+            // candidate, taken when the filter left none (the point then
+            // has its full candidate set and needs no second pass)
+            for (int pass = a.obb ? 0 : 1; pass < 2 && n == 0; ++pass) {
+                for (int q = qb; q < qe; ++q) {
+                    const int e = a.cell_el[q];
+                    const double *b = a.bbox + 6 * (long long)e;
+                    if (x0 < b[0] || x0 > b[1] || x1 < b[2] || x1 > b[3] || x2 < b[4] || x2 > b[5])
+                        continue;
+                    if (ps >= 0 && a.esess && a.esess[e] == ps) continue;
+                    if (pass == 0) {
+                        ++naabb;
+                        const double *o = a.obb + 18 * (long long)e;
+                        const double d0 = x0 - o[9], d1 = x1 - o[10], d2 = x2 - o[11];
+                        bool in = true;
+#pragma unroll
+                        for (int ax = 0; ax < 3; ++ax) {
+                            const double u =
+                                fma(o[3 * ax + 2], d2, fma(o[3 * ax + 1], d1, o[3 * ax] * d0));
+                            in = in && u >= o[12 + ax] && u <= o[15 + ax];
+                        }
+                        if (!in) continue;
+                    }
+                    ce[(long long)n * a.M] = e;
+                    cp[(long long)n * a.M] = atomicAdd(&a.elem_cnt[e], 1);
+                    ++n;
+                }
+                if (pass == 1 || naabb == 0) full = 1;  // the method's whole set
+                if (pass == 0 && naabb == 0) break;     // nothing to take
+            }
         }
+        a.ncand[t] = n | (full << kFullBit);
     }
-    a.ncand[p] = n;
+    if (a.obb) {  // count the method's candidates (first pass covers every point)
+        unsigned long long v = (unsigned long long)naabb;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+        if ((threadIdx.x & (kWave - 1)) == 0 && v) atomicAdd(&a.stats[3], v);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_scatter(LocArgs a)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.npts) return;
-    const int n = a.ncand[p];
-    const long long s0 = (long long)p * a.MC;
+    if (p >= task_count(a)) return;
+    const int n = a.ncand[p] & kCountMask;
     for (int k = 0; k < n; ++k) {
-        const int e = a.cand_el[s0 + k];
-        a.order[a.elem_off[e] + a.cand_pos[s0 + k]] = (int)(s0 + k);
+        const long long s = (long long)k * a.M + p;
+        const int e = a.cand_el[s];
+        a.order[a.elem_off[e] + a.cand_pos[s]] = (int)s;
     }
 }
 
@@ -126,6 +175,174 @@ constexpr double kStepStop = 1e-13;   // accepted step with |s|_inf below this
 constexpr double kStepTiny = 1e-15;   // no progress possible
 constexpr int kMaxIter = 50;
 
+// Projected trust-region Gauss-Newton on phi(r) = ||x(r) - x*||^2 over
+// [-1,1]^3.  A coordinate on a bound whose descent direction points outward
+// is held; the step solves J d = -F when every coordinate is free, else the
+// reduced normal equations on the free ones (steepest descent if singular);
+// it is scaled to the trust radius (max norm) and projected on the cube.
+// rho = actual / predicted decrease; accept if rho >= 0.01; radius doubled
+// (up to 2) when rho > 0.75 and the radius limited the step, set to |s|/4
+// when rho < 0.25.  Stop: phi <= (1e-13 h_e)^2, an accepted step with
+// |s| <= 1e-13, no possible progress, or 50 iterations.
+struct TRNewton {
+    double r[3], F[3], J[9], phi, D, pred, ns;
+    double rt[3];  // next trial point
+    bool limited, have;
+    int it;
+
+    __device__ __forceinline__ void start(const double (&r0)[3])
+    {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            rt[d] = r0[d];
+            r[d] = 0.0;
+            F[d] = 0.0;
+        }
+#pragma unroll
+        for (int d = 0; d < 9; ++d) J[d] = 0.0;
+        phi = INFINITY;
+        D = 1.0;
+        pred = 0.0;
+        ns = 0.0;
+        limited = false;
+        have = false;
+        it = 0;
+    }
+
+    // Consume the map and Jacobian evaluated at rt; returns true when done,
+    // otherwise leaves the next trial point in rt.
+    __device__ __forceinline__ bool update(const double (&xt)[3], const double (&Jt)[9],
+                                           const double (&xs)[3], double rstop)
+    {
+        const double Ft[3] = {xt[0] - xs[0], xt[1] - xs[1], xt[2] - xs[2]};
+        const double phit = fma(Ft[2], Ft[2], fma(Ft[1], Ft[1], Ft[0] * Ft[0]));
+        bool acc = true, stop = false;
+        if (have) {
+            const double rho = (phi - phit) / pred;
+            acc = rho >= 0.01;
+            if (rho > 0.75 && limited)
+                D = fmin(2.0 * D, 2.0);
+            else if (rho < 0.25)
+                D = 0.25 * ns;
+            if (acc && ns <= kStepStop) stop = true;
+        }
+        // branch-free update: the trial Jacobian is consumed on every path,
+        // so its half of the contraction is not sunk into a branch away from
+        // the pipelined node loads
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            r[d] = acc ? rt[d] : r[d];
+            F[d] = acc ? Ft[d] : F[d];
+        }
+#pragma unroll
+        for (int d = 0; d < 9; ++d) J[d] = acc ? Jt[d] : J[d];
+        phi = acc ? phit : phi;
+        have = true;
+        if (stop || phi <= rstop || it >= kMaxIter) return true;
+        ++it;
+        double g[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) g[d] = fma(J[6 + d], F[2], fma(J[3 + d], F[1], J[d] * F[0]));
+        double m[3];
+        int nf = 0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const bool held = (r[d] >= 1.0 && g[d] < 0.0) || (r[d] <= -1.0 && g[d] > 0.0);
+            m[d] = held ? 0.0 : 1.0;
+            nf += held ? 0 : 1;
+        }
+        if (nf == 0) return true;
+        double dl[3];
+        bool ok;
+        if (nf == 3) {
+            const double b[3] = {-F[0], -F[1], -F[2]};
+            ok = solve3(J, b, dl);
+        } else {
+            // reduced normal equations: (M J^T J M + I - M) d = -M g
+            double A[9], b[3];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+#pragma unroll
+                for (int v = 0; v < 3; ++v) {
+                    const double jtj = fma(J[6 + u], J[6 + v], fma(J[3 + u], J[3 + v], J[u] * J[v]));
+                    A[3 * u + v] = m[u] * m[v] * jtj + ((u == v) ? 1.0 - m[u] : 0.0);
+                }
+                b[u] = -m[u] * g[u];
+            }
+            ok = solve3(A, b, dl);
+        }
+        if (!ok) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) dl[d] = -m[d] * g[d];
+        }
+        const double nd = fmax(fabs(dl[0]), fmax(fabs(dl[1]), fabs(dl[2])));
+        if (!(nd > 0.0) || !isfinite(nd)) return true;
+        limited = nd > D;
+        const double sc = limited ? D / nd : 1.0;
+        double s[3];
+        ns = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double v = fmin(1.0, fmax(-1.0, r[d] + dl[d] * sc));
+            rt[d] = v;
+            s[d] = v - r[d];
+            ns = fmax(ns, fabs(s[d]));
+        }
+        double q2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double t =
+                fma(J[3 * c + 2], s[2], fma(J[3 * c + 1], s[1], fma(J[3 * c], s[0], F[c])));
+            q2 = fma(t, t, q2);
+        }
+        pred = phi - q2;
+        return ns <= kStepTiny || !(pred > 0.0);
+    }
+};
+
+// Reference coordinates of GLL node n (i + n1 (j + n1 k)).
+template <int N1>
+__device__ __forceinline__ void node_rst(BasisPtr<double> B, int n, double (&r)[3])
+{
+    const int i0 = n % N1, i1 = (n / N1) % N1, i2 = n / (N1 * N1);
+    r[0] = r[1] = r[2] = 0.0;
+#pragma unroll
+    for (int i = 0; i < N1; ++i) {
+        const double zi = B.z(i);
+        r[0] = (i == i0) ? zi : r[0];
+        r[1] = (i == i1) ? zi : r[1];
+        r[2] = (i == i2) ? zi : r[2];
+    }
+}
+
+// Store one candidate's result (and the distance field if inside).
+template <int N1>
+__device__ __forceinline__ void store_pair(const LocArgs &a, BasisPtr<double> B, int slot, int e,
+                                           const TRNewton &t, double he)
+{
+    constexpr int V = N1 * N1 * N1;
+    double *o = a.res + 4 * (long long)slot;
+    o[0] = t.r[0];
+    o[1] = t.r[1];
+    o[2] = t.r[2];
+    o[3] = t.phi;
+    const bool inside = sqrt(t.phi) <= a.tol * he;
+    a.res_in[slot] = inside ? 1 : 0;
+    if (a.res_dl) {
+        double dl = 0.0;
+        if (inside) {
+            double hr[N1], hs[N1], ht[N1];
+            lagrange<N1>(B, t.r[0], hr);
+            lagrange<N1>(B, t.r[1], hs);
+            lagrange<N1>(B, t.r[2], ht);
+            dl = field_value_v<N1>(a.delta + (long long)e * V, hr, hs, ht);
+        }
+        a.res_dl[slot] = dl;
+    }
+}
+
+// One 64-lane wavefront per element, node rows from the scalar cache (used
+// for orders above 9, whose element block does not fit the LDS budget).
 template <int N1>
 __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__restrict__ basis)
 {
@@ -143,7 +360,8 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
         const int q = base + (int)threadIdx.x;
         const bool act = q < end;
         const int slot = act ? a.order[q] : 0;
-        const int p = slot / a.MC;
+        const int tk = slot % a.M;
+        const int p = a.idx ? a.idx[tk] : tk;
         double xs[3] = {0.0, 0.0, 0.0};
         if (act) {
             xs[0] = a.pts[3 * (long long)p];
@@ -162,145 +380,19 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
                 bq = n;
             }
         }
-        double rt[3];
-        {
-            const int i0 = bq % N1, i1 = (bq / N1) % N1, i2 = bq / (N1 * N1);
-            rt[0] = rt[1] = rt[2] = 0.0;
-#pragma unroll
-            for (int i = 0; i < N1; ++i) {
-                const double zi = B.z(i);
-                rt[0] = (i == i0) ? zi : rt[0];
-                rt[1] = (i == i1) ? zi : rt[1];
-                rt[2] = (i == i2) ? zi : rt[2];
-            }
-        }
-
-        // projected trust-region Gauss-Newton: a coordinate on a bound of
-        // [-1,1]^3 whose descent direction points outward is held; the
-        // trust radius is measured in the max norm
-        double r[3] = {0, 0, 0}, F[3] = {0, 0, 0}, J[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-        double phi = INFINITY, D = 1.0, pred = 0.0, ns = 0.0;
-        bool limited = false, have = false;
-        int it = 0;
+        double r0[3];
+        node_rst<N1>(B, bq, r0);
+        TRNewton t;
+        t.start(r0);
         bool done = !act;
         while (!done) {
             double xt[3], Jt[9];
-            geo_eval<N1>(X, B, rt, xt, Jt);
-            const double Ft[3] = {xt[0] - xs[0], xt[1] - xs[1], xt[2] - xs[2]};
-            const double phit = fma(Ft[2], Ft[2], fma(Ft[1], Ft[1], Ft[0] * Ft[0]));
-            bool acc = true, stop = false;
-            if (have) {
-                const double rho = (phi - phit) / pred;
-                acc = rho >= 0.01;
-                if (rho > 0.75 && limited)
-                    D = fmin(2.0 * D, 2.0);
-                else if (rho < 0.25)
-                    D = 0.25 * ns;
-                if (acc && ns <= kStepStop) stop = true;
-            }
-            // branch-free update: the trial Jacobian is consumed on every path,
-            // so its half of the contraction is not sunk into a branch away
-            // from the pipelined node loads
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                r[d] = acc ? rt[d] : r[d];
-                F[d] = acc ? Ft[d] : F[d];
-            }
-#pragma unroll
-            for (int d = 0; d < 9; ++d) J[d] = acc ? Jt[d] : J[d];
-            phi = acc ? phit : phi;
-            have = true;
-            if (!stop && (phi <= rstop || it >= kMaxIter)) stop = true;
-            if (!stop) {
-                ++it;
-                double g[3];
-#pragma unroll
-                for (int d = 0; d < 3; ++d)
-                    g[d] = fma(J[6 + d], F[2], fma(J[3 + d], F[1], J[d] * F[0]));
-                double m[3];
-                int nf = 0;
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    const bool held = (r[d] >= 1.0 && g[d] < 0.0) || (r[d] <= -1.0 && g[d] > 0.0);
-                    m[d] = held ? 0.0 : 1.0;
-                    nf += held ? 0 : 1;
-                }
-                if (nf == 0) {
-                    stop = true;
-                } else {
-                    double dl[3];
-                    bool ok;
-                    if (nf == 3) {
-                        const double b[3] = {-F[0], -F[1], -F[2]};
-                        ok = solve3(J, b, dl);
-                    } else {
-                        // reduced normal equations: (M J^T J M + I - M) d = -M g
-                        double A[9], b[3];
-#pragma unroll
-                        for (int u = 0; u < 3; ++u) {
-#pragma unroll
-                            for (int v = 0; v < 3; ++v) {
-                                const double jtj =
-                                    fma(J[6 + u], J[6 + v], fma(J[3 + u], J[3 + v], J[u] * J[v]));
-                                A[3 * u + v] = m[u] * m[v] * jtj + ((u == v) ? 1.0 - m[u] : 0.0);
-                            }
-                            b[u] = -m[u] * g[u];
-                        }
-                        ok = solve3(A, b, dl);
-                    }
-                    if (!ok) {
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) dl[d] = -m[d] * g[d];
-                    }
-                    const double nd = fmax(fabs(dl[0]), fmax(fabs(dl[1]), fabs(dl[2])));
-                    if (!(nd > 0.0) || !isfinite(nd)) {
-                        stop = true;
-                    } else {
-                        limited = nd > D;
-                        const double sc = limited ? D / nd : 1.0;
-                        double s[3];
-                        ns = 0.0;
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) {
-                            const double v = fmin(1.0, fmax(-1.0, r[d] + dl[d] * sc));
-                            rt[d] = v;
-                            s[d] = v - r[d];
-                            ns = fmax(ns, fabs(s[d]));
-                        }
-                        double q2 = 0.0;
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) {
-                            const double t =
-                                fma(J[3 * c + 2], s[2], fma(J[3 * c + 1], s[1], fma(J[3 * c], s[0], F[c])));
-                            q2 = fma(t, t, q2);
-                        }
-                        pred = phi - q2;
-                        if (ns <= kStepTiny || !(pred > 0.0)) stop = true;
-                    }
-                }
-            }
-            done = stop;
+            geo_eval<N1>(X, B, t.rt, xt, Jt);
+            done = t.update(xt, Jt, xs, rstop);
         }
         if (act) {
-            my_iters += (unsigned long long)it;
-            double *o = a.res + 4 * (long long)slot;
-            o[0] = r[0];
-            o[1] = r[1];
-            o[2] = r[2];
-            o[3] = phi;
-            const bool inside = sqrt(phi) <= a.tol * he;
-            a.res_in[slot] = inside ? 1 : 0;
-            if (a.res_dl) {
-                double dl = 0.0;
-                if (inside) {
-                    double hr[N1], hs[N1], ht[N1];
-                    lagrange<N1>(B, r[0], hr);
-                    lagrange<N1>(B, r[1], hs);
-                    lagrange<N1>(B, r[2], ht);
-                    dl = field_value<N1>(as_const(a.delta + (long long)e * V), hr, hs, ht);
-                }
-                a.res_dl[slot] = dl;
-            }
+            my_iters += (unsigned long long)t.it;
+            store_pair<N1>(a, B, slot, e, t, he);
         }
     }
     // wave totals -> counters
@@ -312,18 +404,141 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
     }
 }
 
+// Element groups staged in LDS.  A 256-thread block owns G consecutive
+// elements and every (point, element) pair of them (contiguous in the
+// element-grouped order).  After staging the G element blocks (each padded
+// by 16 bytes so that lanes reading different elements hit different LDS
+// banks), the block first finds every pair's closest node (full-width
+// scans), then runs Newton with lane refill: a lane that finishes its pair
+// takes the next unstarted pair of the group, so lanes stay busy while
+// iteration counts differ.
+constexpr int kGrpThreads = 256;
+
+template <int N1>
+struct Group {
+    static constexpr int V = N1 * N1 * N1;
+    static constexpr int stride = 3 * V + 2;  // doubles per staged element
+    static constexpr int G = (3 * V * 8 <= 6 * 1024) ? 8 : (3 * V * 8 <= 12 * 1024 ? 4 : 2);
+    static constexpr int lds_bytes = G * stride * 8;
+};
+
+template <int N1>
+__global__ __launch_bounds__(kGrpThreads) void k_locate_grp(LocArgs a,
+                                                          const double *__restrict__ basis,
+                                                          int E)
+{
+    using Gr = Group<N1>;
+    constexpr int V = Gr::V, G = Gr::G, S = Gr::stride;
+    __shared__ double sX[G * S];
+    __shared__ int next;
+    const BasisPtr<double> B{as_const(basis)};
+    const int e0 = blockIdx.x * G;
+    const int ne = min(G, E - e0);
+    const int pb = a.elem_off[e0], pe = a.elem_off[e0 + ne];
+    const int count = pe - pb;
+    if (count <= 0) return;  // uniform across the block
+    // stage the elements that have pairs (others are never read)
+    for (int g = 0; g < ne; ++g) {
+        if (a.elem_off[e0 + g + 1] == a.elem_off[e0 + g]) continue;
+        const double2 *src = (const double2 *)(a.geom + (long long)(e0 + g) * 3 * V);
+        double *dst = sX + g * S;
+        for (int q = threadIdx.x; q < 3 * V / 2; q += kGrpThreads) {
+            const double2 v = src[q];
+            dst[2 * q] = v.x;
+            dst[2 * q + 1] = v.y;
+        }
+        if ((3 * V) & 1) {
+            if (threadIdx.x == 0) dst[3 * V - 1] = a.geom[(long long)(e0 + g) * 3 * V + 3 * V - 1];
+        }
+    }
+    if (threadIdx.x == 0) next = kGrpThreads;
+    __syncthreads();
+
+    // closest node of every pair (stored in cand_pos, free after the scatter)
+    for (int u = threadIdx.x; u < count; u += kGrpThreads) {
+        const int slot = a.order[pb + u];
+        const int tk = slot % a.M;
+        const int p = a.idx ? a.idx[tk] : tk;
+        const int g = a.cand_el[slot] - e0;
+        const double x0 = a.pts[3 * (long long)p], x1 = a.pts[3 * (long long)p + 1],
+                     x2 = a.pts[3 * (long long)p + 2];
+        lptr<double> X = (lptr<double>)(sX + g * S);
+        double best = INFINITY;
+        int bq = 0;
+#pragma unroll 8
+        for (int n = 0; n < V; ++n) {
+            const double dx = X[n] - x0, dy = X[V + n] - x1, dz = X[2 * V + n] - x2;
+            const double d = fma(dz, dz, fma(dy, dy, dx * dx));
+            if (d < best) {
+                best = d;
+                bq = n;
+            }
+        }
+        a.cand_pos[slot] = bq;
+    }
+    __syncthreads();
+
+    // Newton with lane refill
+    unsigned long long my_iters = 0;
+    int u = threadIdx.x;
+    int slot = 0, g = 0;
+    double xs[3] = {0.0, 0.0, 0.0}, he = 0.0, rstop = 0.0;
+    TRNewton t;
+    auto begin_pair = [&](int uu) {
+        slot = a.order[pb + uu];
+        const int tk = slot % a.M;
+        const int p = a.idx ? a.idx[tk] : tk;
+        g = a.cand_el[slot] - e0;
+        xs[0] = a.pts[3 * (long long)p];
+        xs[1] = a.pts[3 * (long long)p + 1];
+        xs[2] = a.pts[3 * (long long)p + 2];
+        he = a.esize[e0 + g];
+        rstop = (kResidStop * he) * (kResidStop * he);
+        double r0[3];
+        node_rst<N1>(B, a.cand_pos[slot], r0);
+        t.start(r0);
+    };
+    if (u < count) begin_pair(u);
+    while (u < count) {
+        double xt[3], Jt[9];
+        geo_eval_lds<N1>((lptr<double>)(sX + g * S), B, t.rt, xt, Jt);
+        if (t.update(xt, Jt, xs, rstop)) {
+            my_iters += (unsigned long long)t.it;
+            store_pair<N1>(a, B, slot, e0 + g, t, he);
+            u = atomicAdd(&next, 1);
+            if (u < count) begin_pair(u);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) my_iters += __shfl_xor(my_iters, o, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        atomicAdd(&a.stats[1], my_iters);
+        if (threadIdx.x == 0) atomicAdd(&a.stats[0], (unsigned long long)count);
+    }
+}
+
 // Owner selection per point (candidates are in ascending element order).
 __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ code,
                                                 int *__restrict__ el, double *__restrict__ rst,
                                                 double *__restrict__ dist2)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.npts) return;
-    const int n = a.ncand[p];
-    const long long s0 = (long long)p * a.MC;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = t < task_count(a);
+    if (a.obb) {  // first pass covers every point once: count them
+        unsigned long long v = live ? 1ULL : 0ULL;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+        if ((threadIdx.x & (kWave - 1)) == 0 && v) atomicAdd(&a.stats[2], v);
+    }
+    if (!live) return;
+    const int p = a.idx ? a.idx[t] : t;
+    const int nv = a.ncand[t];
+    const int n = nv & kCountMask;
+    const bool full = (nv >> kFullBit) != 0;
+    auto S =[&](int k) { return (long long)k * a.M + t; };
     int w = -1, c = 2;
     bool anyin = false;
-    for (int k = 0; k < n; ++k) anyin |= a.res_in[s0 + k] != 0;
+    for (int k = 0; k < n; ++k) anyin |= a.res_in[S(k)] != 0;
     if (anyin) {
         c = 0;
         if (a.res_dl) {
@@ -333,13 +548,13 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
             double bd = -INFINITY;
             bool hv = false;
             for (int k = 0; k < n; ++k) {
-                if (!a.res_in[s0 + k]) continue;
-                const int sk = a.esess ? a.esess[a.cand_el[s0 + k]] : 0;
+                if (!a.res_in[S(k)]) continue;
+                const int sk = a.esess ? a.esess[a.cand_el[S(k)]] : 0;
                 double sd = -INFINITY;
                 for (int u = 0; u < n; ++u) {
-                    if (!a.res_in[s0 + u]) continue;
-                    const int su = a.esess ? a.esess[a.cand_el[s0 + u]] : 0;
-                    if (su == sk) sd = fmax(sd, a.res_dl[s0 + u]);
+                    if (!a.res_in[S(u)]) continue;
+                    const int su = a.esess ? a.esess[a.cand_el[S(u)]] : 0;
+                    if (su == sk) sd = fmax(sd, a.res_dl[S(u)]);
                 }
                 if (!hv || sd > bd || (sd == bd && sk < bs)) {
                     hv = true;
@@ -348,19 +563,19 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
                 }
             }
             for (int k = 0; k < n && w < 0; ++k) {
-                if (!a.res_in[s0 + k]) continue;
-                const int sk = a.esess ? a.esess[a.cand_el[s0 + k]] : 0;
+                if (!a.res_in[S(k)]) continue;
+                const int sk = a.esess ? a.esess[a.cand_el[S(k)]] : 0;
                 if (sk == bs) w = k;
             }
         } else {
             for (int k = 0; k < n && w < 0; ++k)
-                if (a.res_in[s0 + k]) w = k;
+                if (a.res_in[S(k)]) w = k;
         }
     } else if (n > 0) {
         c = 1;
         w = 0;
         for (int k = 1; k < n; ++k) {
-            const double dk = a.res[4 * (s0 + k) + 3], dw = a.res[4 * (s0 + w) + 3];
+            const double dk = a.res[4 * (S(k)) + 3], dw = a.res[4 * (S(w)) + 3];
             const bool tie = fabs(dk - dw) <= 1e-14 * fmax(dk, dw);
             if (!tie && dk < dw) w = k;  // ties keep the earlier (smaller) id
         }
@@ -371,14 +586,14 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
         rst[3 * (long long)p] = rst[3 * (long long)p + 1] = rst[3 * (long long)p + 2] = 0.0;
         dist2[p] = INFINITY;
     } else {
-        const double *o = a.res + 4 * (s0 + w);
-        el[p] = a.cand_el[s0 + w];
+        const double *o = a.res + 4 * (S(w));
+        el[p] = a.cand_el[S(w)];
         rst[3 * (long long)p] = o[0];
         rst[3 * (long long)p + 1] = o[1];
         rst[3 * (long long)p + 2] = o[2];
         dist2[p] = o[3];
     }
-    atomicAdd(&a.stats[2], 1ULL);
+    if (a.obb && c != 0 && !full) a.redo[atomicAdd(a.redo_n, 1)] = p;
 }
 
 #define FP_DISPATCH_N1(n1, MACRO) \
@@ -403,8 +618,29 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
 
 static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, hipStream_t s)
 {
+#define FP_LAUNCH_GRP(N1)                                                                 \
+    k_locate_grp<N1><<<(h->E + Group<N1>::G - 1) / Group<N1>::G, kGrpThreads, 0, s>>>(a, \
+                                                                              h->d_basis, h->E)
 #define FP_LAUNCH_LOCATE(N1) k_locate<N1><<<h->E, kWave, 0, s>>>(a, h->d_basis)
-    FP_DISPATCH_N1(h->n1, FP_LAUNCH_LOCATE);
+    switch (h->n1) {
+        case 2: FP_LAUNCH_GRP(2); break;
+        case 3: FP_LAUNCH_GRP(3); break;
+        case 4: FP_LAUNCH_GRP(4); break;
+        case 5: FP_LAUNCH_GRP(5); break;
+        case 6: FP_LAUNCH_GRP(6); break;
+        case 7: FP_LAUNCH_GRP(7); break;
+        case 8: FP_LAUNCH_GRP(8); break;
+        case 9: FP_LAUNCH_GRP(9); break;
+        case 10: FP_LAUNCH_GRP(10); break;
+        case 11: FP_LAUNCH_LOCATE(11); break;
+        case 12: FP_LAUNCH_LOCATE(12); break;
+        case 13: FP_LAUNCH_LOCATE(13); break;
+        case 14: FP_LAUNCH_LOCATE(14); break;
+        case 15: FP_LAUNCH_LOCATE(15); break;
+        case 16: FP_LAUNCH_LOCATE(16); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef FP_LAUNCH_GRP
 #undef FP_LAUNCH_LOCATE
     return hipGetLastError();
 }
@@ -456,7 +692,7 @@ extern "C" int findpts(fp_handle *h, int npts, const double *pts, const int *pt_
         a.pts = pts + 3 * (long long)start;
         a.psess = pt_session ? pt_session + start : nullptr;
         a.npts = n;
-        a.MC = h->MC;
+        a.M = h->max_points;
         a.tol = h->tol;
         a.ncand = h->ncand;
         a.cand_el = h->cand_el;
@@ -478,6 +714,14 @@ extern "C" int findpts(fp_handle *h, int npts, const double *pts, const int *pt_
             FP_HIP(hipEventRecord(t0, s));
         }
         const int pb = (n + 255) / 256;
+        int *co = code + start, *eo = el + start;
+        double *ro = rst + 3 * (long long)start, *dO = dist2 + start;
+        // first pass: oriented-box candidates; points without an inside
+        // candidate go to the redo list
+        a.obb = h->obb;
+        a.redo = h->redo;
+        a.redo_n = h->redo_n;
+        FP_HIP(fill_int(h->redo_n, 0, 1, s));
         FP_HIP(fill_int(h->elem_cnt, 0, (long long)h->E + 1, s));
         k_cand<<<pb, 256, 0, s>>>(a);
         FP_HIP(hipGetLastError());
@@ -487,8 +731,21 @@ extern "C" int findpts(fp_handle *h, int npts, const double *pts, const int *pt_
         if (h->timing) FP_HIP(hipEventRecord(l0, s));
         FP_HIP(launch_locate_kernel(h, a, s));
         if (h->timing) FP_HIP(hipEventRecord(l1, s));
-        k_select<<<pb, 256, 0, s>>>(a, code + start, el + start, rst + 3 * (long long)start,
-                                   dist2 + start);
+        k_select<<<pb, 256, 0, s>>>(a, co, eo, ro, dO);
+        FP_HIP(hipGetLastError());
+        // second pass over the redo list with the axis-aligned candidates
+        // only (sized on the device: kernels past the count return at once)
+        a.obb = nullptr;
+        a.idx = h->redo;
+        a.dcount = h->redo_n;
+        FP_HIP(fill_int(h->elem_cnt, 0, (long long)h->E + 1, s));
+        k_cand<<<pb, 256, 0, s>>>(a);
+        FP_HIP(hipGetLastError());
+        FP_HIP(scan_exclusive(h->elem_cnt, h->elem_off, h->E, h->scan_tmp, s));
+        k_scatter<<<pb, 256, 0, s>>>(a);
+        FP_HIP(hipGetLastError());
+        FP_HIP(launch_locate_kernel(h, a, s));
+        k_select<<<pb, 256, 0, s>>>(a, co, eo, ro, dO);
         FP_HIP(hipGetLastError());
         if (h->timing) {
             FP_HIP(hipEventRecord(t1, s));

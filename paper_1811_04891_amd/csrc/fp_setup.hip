@@ -222,6 +222,114 @@ __global__ __launch_bounds__(kWave) void k_bbox(const double *__restrict__ geom,
     }
 }
 
+// Oriented box of each element (one wave per element).  Frame: Gram-Schmidt
+// of the mean edge vectors along r, s, t (identity if they are degenerate).
+// The rotated coordinates u = Q (x - centre) are linear in x, so the
+// Bernstein coefficients of their nodal values bound the element in that
+// frame exactly as the axis-aligned box does; any Q (orthonormal or not)
+// keeps this rigorous.  Same margin as the axis-aligned box.
+__global__ __launch_bounds__(kWave) void k_obb(const double *__restrict__ geom, int n1,
+                                               const double *__restrict__ binv,
+                                               const double *__restrict__ bbox,
+                                               const double *__restrict__ esize,
+                                               double *__restrict__ obb)
+{
+    extern __shared__ double sh[];
+    const int V = n1 * n1 * n1;
+    double *A = sh, *B = sh + V;
+    __shared__ double Bi[kMaxN1 * kMaxN1];
+    const int e = blockIdx.x, t = threadIdx.x;
+    for (int q = t; q < n1 * n1; q += kWave) Bi[q] = binv[q];
+    const double *X = geom + (long long)e * 3 * V;
+    // mean edge vectors (lane-parallel sums over the n1^2 node lines)
+    double ed[3][3];
+    for (int c = 0; c < 3; ++c) {
+        double sr = 0.0, ss = 0.0, st = 0.0;
+        for (int q = t; q < n1 * n1; q += kWave) {
+            const int a = q % n1, b = q / n1;
+            const double *Xc = X + c * V;
+            sr += Xc[n1 - 1 + n1 * (a + n1 * b)] - Xc[n1 * (a + n1 * b)];
+            ss += Xc[a + n1 * (n1 - 1 + n1 * b)] - Xc[a + n1 * n1 * b];
+            st += Xc[a + n1 * (b + n1 * (n1 - 1))] - Xc[a + n1 * b];
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            sr += __shfl_xor(sr, o, kWave);
+            ss += __shfl_xor(ss, o, kWave);
+            st += __shfl_xor(st, o, kWave);
+        }
+        ed[0][c] = sr;
+        ed[1][c] = ss;
+        ed[2][c] = st;
+    }
+    double Q[3][3];
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+        double v[3] = {ed[a][0], ed[a][1], ed[a][2]};
+        for (int b = 0; b < a; ++b) {
+            const double d = v[0] * Q[b][0] + v[1] * Q[b][1] + v[2] * Q[b][2];
+            for (int c = 0; c < 3; ++c) v[c] -= d * Q[b][c];
+        }
+        const double nv = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        const double ne = sqrt(ed[a][0] * ed[a][0] + ed[a][1] * ed[a][1] + ed[a][2] * ed[a][2]);
+        ok = ok && isfinite(nv) && nv > 1e-6 * ne && ne > 0.0;
+        for (int c = 0; c < 3; ++c) Q[a][c] = ok ? v[c] / nv : 0.0;
+    }
+    if (!ok)
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) Q[a][c] = (a == c) ? 1.0 : 0.0;
+    const double *bb = bbox + 6 * (long long)e;
+    const double ctr[3] = {0.5 * (bb[0] + bb[1]), 0.5 * (bb[2] + bb[3]), 0.5 * (bb[4] + bb[5])};
+    double lo[3], hi[3], amax = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        for (int q = t; q < V; q += kWave) {
+            const double u = Q[a][0] * (X[q] - ctr[0]) + Q[a][1] * (X[V + q] - ctr[1]) +
+                             Q[a][2] * (X[2 * V + q] - ctr[2]);
+            A[q] = u;
+            amax = fmax(amax, fabs(u));
+        }
+        __syncthreads();
+        for (int q = t; q < V; q += kWave) {  // along r
+            int i = q % n1, rest = q - i;
+            double s = 0.0;
+            for (int l = 0; l < n1; ++l) s = fma(Bi[i * n1 + l], A[rest + l], s);
+            B[q] = s;
+        }
+        __syncthreads();
+        for (int q = t; q < V; q += kWave) {  // along s
+            int i = q % n1, j = (q / n1) % n1, k = q / (n1 * n1);
+            double s = 0.0;
+            for (int l = 0; l < n1; ++l) s = fma(Bi[j * n1 + l], B[i + n1 * (l + n1 * k)], s);
+            A[q] = s;
+        }
+        __syncthreads();
+        double cmn = INFINITY, cmx = -INFINITY;
+        for (int q = t; q < V; q += kWave) {  // along t
+            int ij = q % (n1 * n1), k = q / (n1 * n1);
+            double s = 0.0;
+            for (int l = 0; l < n1; ++l) s = fma(Bi[k * n1 + l], A[ij + n1 * n1 * l], s);
+            cmn = fmin(cmn, s);
+            cmx = fmax(cmx, s);
+        }
+        lo[a] = wave_min(cmn);
+        hi[a] = wave_max(cmx);
+        __syncthreads();
+    }
+    amax = wave_max(amax);
+    if (t == 0) {
+        const double cabs = fmax(fabs(ctr[0]), fmax(fabs(ctr[1]), fabs(ctr[2])));
+        const double m = 1e-8 * esize[e] + 1e-14 * (amax + cabs);
+        double *o = obb + 18 * (long long)e;
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) o[3 * a + c] = Q[a][c];
+        for (int c = 0; c < 3; ++c) {
+            o[9 + c] = ctr[c];
+            o[12 + c] = lo[c] - m;
+            o[15 + c] = hi[c] + m;
+        }
+    }
+}
+
 // Union of the element boxes (one block).
 __global__ __launch_bounds__(256) void k_gbox(const double *__restrict__ bbox, int E,
                                               double *__restrict__ out)
@@ -313,9 +421,9 @@ using namespace fp;
 
 static void release(fp_handle *h)
 {
-    void *ptrs[] = {h->d_basis, h->d_basis32, h->geom, h->geom32, h->esize, h->bbox, h->esess, h->delta,
+    void *ptrs[] = {h->d_basis, h->d_basis32, h->geom, h->geom32, h->esize, h->bbox, h->obb, h->esess, h->delta,
                     h->cell_off, h->cell_el, h->ncand, h->cand_el, h->cand_pos,
-                    h->elem_cnt, h->elem_off, h->order, h->res, h->res_dl, h->res_in,
+                    h->elem_cnt, h->elem_off, h->order, h->res, h->res_dl, h->res_in, h->redo, h->redo_n,
                     h->scan_tmp, h->ev_cnt, h->ev_off, h->ev_pos, h->ev_order, h->stats};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -399,6 +507,7 @@ extern "C" int findpts_setup(fp_handle **out, const double *x, const double *y,
     FP_HIP_H(dalloc(h, &h->geom32, 3 * EV));  // kept for either precision
     FP_HIP_H(dalloc(h, &h->esize, E));
     FP_HIP_H(dalloc(h, &h->bbox, 6 * (size_t)E));
+    FP_HIP_H(dalloc(h, &h->obb, 18 * (size_t)E));
     FP_HIP_H(dalloc(h, &h->stats, 4));
     FP_HIP_H(dalloc(h, &h->d_basis, 2 * kMaxN1));
     FP_HIP_H(dalloc(h, &h->d_basis32, 2 * kMaxN1));
@@ -430,6 +539,9 @@ extern "C" int findpts_setup(fp_handle **out, const double *x, const double *y,
     k_bbox<<<E, kWave, 2 * V * sizeof(double), s>>>(h->geom, (int)n1, d_binv, h->bbox,
                                                      h->esize);
     FP_HIP_H(hipGetLastError());
+    k_obb<<<E, kWave, 2 * V * sizeof(double), s>>>(h->geom, (int)n1, d_binv, h->bbox,
+                                                    h->esize, h->obb);
+    FP_HIP_H(hipGetLastError());
     k_gbox<<<1, 256, 0, s>>>(h->bbox, E, d_g);
     FP_HIP_H(hipGetLastError());
     double gb[6];
@@ -446,7 +558,8 @@ extern "C" int findpts_setup(fp_handle **out, const double *x, const double *y,
         return FP_EINVAL;
     }
 
-    // hash grid: about E cells, cell aspect following the extents
+    // hash grid: about 8 E cells (two per element and axis, so each cell
+    // lists few elements), cell aspect following the extents
     Grid g{};
     double ext[3], vol = 1.0;
     for (int a = 0; a < 3; ++a) {
@@ -456,7 +569,7 @@ extern "C" int findpts_setup(fp_handle **out, const double *x, const double *y,
         if (!(ext[a] > 0.0)) ext[a] = 1e-300;
         vol *= ext[a];
     }
-    const double dens = std::cbrt((double)E / vol);
+    const double dens = std::cbrt(8.0 * (double)E / vol);
     for (int a = 0; a < 3; ++a) {
         double n = std::floor(ext[a] * dens + 0.5);
         n = std::min(std::max(n, 1.0), 1024.0);
@@ -512,6 +625,8 @@ extern "C" int findpts_setup(fp_handle **out, const double *x, const double *y,
     FP_HIP_H(dalloc(h, &h->order, M * MC));
     FP_HIP_H(dalloc(h, &h->res, M * MC * 4));
     FP_HIP_H(dalloc(h, &h->res_in, M * MC));
+    FP_HIP_H(dalloc(h, &h->redo, M));
+    FP_HIP_H(dalloc(h, &h->redo_n, 1));
     if (h->delta) FP_HIP_H(dalloc(h, &h->res_dl, M * MC));
     FP_HIP_H(dalloc(h, &h->ev_cnt, (size_t)E + 1));
     FP_HIP_H(dalloc(h, &h->ev_off, (size_t)E + 1));
@@ -549,7 +664,7 @@ extern "C" int findpts_stats(fp_handle *h, long long *h_counts, int reset)
     unsigned long long v[4];
     FP_HIP(hipDeviceSynchronize());
     FP_HIP(hipMemcpy(v, h->stats, sizeof v, hipMemcpyDeviceToHost));
-    for (int i = 0; i < 3; ++i) h_counts[i] = (long long)v[i];
+    for (int i = 0; i < 4; ++i) h_counts[i] = (long long)v[i];
     if (reset) FP_HIP(hipMemset(h->stats, 0, sizeof v));
     return FP_OK;
 }

@@ -180,8 +180,9 @@ def findpts_set_precision(h: Handle, precision: int):
 
 
 def findpts_stats(h: Handle, reset: bool = False):
-    """(pairs examined, Newton iterations, points located) since setup/reset."""
-    v = (C.c_longlong * 3)()
+    """(pairs solved, Newton iterations, points located, method candidates)
+    since setup/reset."""
+    v = (C.c_longlong * 4)()
     _check(lib().findpts_stats(h.ptr, v, int(bool(reset))), "findpts_stats")
     return tuple(v)
 

@@ -62,10 +62,11 @@ def test_c1_unit_cube_full(dev):
     assert st["inside"] == len(pts)
     ref = om.eval(g[0], g[1], g[2], [f.numpy()])
     compare_eval(out, ref, [f.numpy()])
-    # pairs examined = oracle candidate count (integer work, exact)
-    pairs, iters, npts = fp.findpts_stats(h)
-    assert pairs == om.last_stats[0] and npts == len(pts)
-    _say(f"c1 ok {st}, gpu newton iters/pair {iters / pairs:.2f} oracle {om.last_stats[1] / om.last_stats[0]:.2f}")
+    # candidates of the method (hash + box + session) = oracle count (exact)
+    pairs, iters, npts, cands = fp.findpts_stats(h)
+    assert cands == om.last_stats[0] and npts == len(pts)
+    _say(f"c1 ok {st}, gpu pairs/pt {pairs / npts:.3f} iters/pair {iters / pairs:.2f}; "
+         f"oracle cands/pt {cands / npts:.3f} iters/cand {om.last_stats[1] / om.last_stats[0]:.2f}")
 
 
 def test_setup_boxes_and_hash(dev):
@@ -124,9 +125,9 @@ def test_c2_annulus_subset(dev, c2):
     assert st["border"] > 0 and st["notfound"] > 0
     ref = om.eval(g[0], g[1], g[2], [f.numpy() for f in fields])
     compare_eval(out, ref, [f.numpy() for f in fields])
-    pairs, _, _ = fp.findpts_stats(h)
-    assert pairs == om.last_stats[0]
-    _say(f"c2 subset ok {st}")
+    pairs, _, npts, cands = fp.findpts_stats(h)
+    assert cands == om.last_stats[0] and npts == len(sub)
+    _say(f"c2 subset ok {st}; pairs solved/pt {pairs / npts:.3f}, method cands/pt {cands / npts:.3f}")
 
 
 def test_c2_full_size_sampled(dev, c2):
