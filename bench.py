@@ -45,7 +45,7 @@ def eval_flops_per_point(N, nf):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("fp_locate.hip", "fp_basis.h"):
+    for f in ("fp_locate.hip", "fp_mfma.inc", "fp_basis.h"):
         with open(os.path.join(ROOT, "paper_1811_04891_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -103,6 +103,8 @@ def main():
                     help="in-annulus points (1 %% more are placed outside)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
+                    help="precision of the headline line (the other one is timed beside it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -140,27 +142,44 @@ def main():
         fp.findpts(h, pts, None, code, el, rst, d2)
         fp.findpts_eval(h, code, el, rst, fields, out)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    fp.findpts_stats(h, reset=True)
-    fp.findpts_timing(h, True)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
-    fp.findpts_timing(h, False)
-    tim = fp.findpts_timing_read(h)
-    pairs, iters, located, cands = fp.findpts_stats(h)
-    ms_per_step = total_ms / args.steps
+    def timed(prec):
+        fp.findpts_set_precision(h, prec)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        fp.findpts_stats(h, reset=True)
+        fp.findpts_timing(h, True)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            step()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        total_ms = ev0.elapsed_time(ev1)
+        fp.findpts_timing(h, False)
+        tim = fp.findpts_timing_read(h)
+        counts = fp.findpts_stats(h)
+        ms = total_ms / args.steps
+        res = (code.cpu().numpy(), el.cpu().numpy(), rst.cpu().numpy(), d2.cpu().numpy())
+        print(f"# {'mixed' if prec else 'fp64'}: {ms:.3f} ms/step, {P / ms * 1e3:.4g} points/s; "
+              f"kernels {tim}", file=sys.stderr, flush=True)
+        return ms, tim, counts, res
+
+    head = fp.FP_PREC_MIXED if args.precision == "mixed" else fp.FP_PREC_FP64
+    other = fp.FP_PREC_FP64 if head == fp.FP_PREC_MIXED else fp.FP_PREC_MIXED
+    ms_o, tim_o, counts_o, res_o = timed(other)
+    ms_per_step, tim, (pairs, iters, located, cands), res_h = timed(head)
     value = P / (ms_per_step / 1e3)
-    print(f"# {ms_per_step:.3f} ms/step, {value:.4g} points/s; kernels {tim}", file=sys.stderr,
-          flush=True)
-    codes = np.bincount(code.cpu().numpy(), minlength=3)
+    codes = np.bincount(res_h[0], minlength=3)
+    # agreement of the two precisions on this workload
+    res64, resmx = (res_h, res_o) if head == fp.FP_PREC_FP64 else (res_o, res_h)
+    same_el = res64[1] == resmx[1]
+    agree = {
+        "codes_equal": bool(np.array_equal(res64[0], resmx[0])),
+        "elements_differ": int(np.sum(~same_el)),
+        "max_abs_dr": float(np.max(np.abs(res64[2][same_el] - resmx[2][same_el]))),
+    }
 
     cb = None
     if not args.no_cpu_baseline:
@@ -189,17 +208,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if head == fp.FP_PREC_FP64 else "f32+f64",
         "data": "synthetic",
         "config": {
             "workload": "annulus_c2: 16,384 curved hexes N=7 (64x16x16, exact arcs), "
-                        f"{P} query points (1% outside), 4 f64 fields; findpts+findpts_eval, FP64",
-            "E": mesh.E, "N": N, "points": P, "fields": 4, "precision": "fp64",
+                        f"{P} query points (1% outside), 4 f64 fields; findpts+findpts_eval, "
+                        f"{args.precision}",
+            "E": mesh.E, "N": N, "points": P, "fields": 4, "precision": args.precision,
             "parallelism": "single GPU",
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "k_locate_grp (trust-region Newton, LDS-staged element groups)",
+            "kernel": "k_locate_mfma (trust-region Newton on FP64 matrix cores)",
             "achieved": achieved,
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
@@ -221,6 +241,13 @@ def main():
                        "method_candidates_per_point": cands / max(located, 1),
                        "codes": codes.tolist()},
     }
+    oname = "mixed" if other == fp.FP_PREC_MIXED else "fp64"
+    rec[oname] = {
+        "value": P / (ms_o / 1e3), "ms_per_step": ms_o,
+        "locate_kernel_ms": tim_o["locate_kernel"][0] / max(tim_o["locate_kernel"][1], 1),
+        "newton_iters_per_pair": counts_o[1] / max(counts_o[0], 1),
+    }
+    rec["fp64_vs_mixed"] = agree
     if cb:
         rec["cpu_baseline"] = {
             "value": cb["n"] / cb["seconds"],

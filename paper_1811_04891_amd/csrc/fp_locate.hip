@@ -187,6 +187,8 @@ constexpr int kMaxIter = 50;
 struct TRNewton {
     double r[3], F[3], J[9], phi, D, pred, ns;
     double rt[3];  // next trial point
+    double step_stop = kStepStop;
+    int max_it = kMaxIter;
     bool limited, have;
     int it;
 
@@ -224,7 +226,7 @@ struct TRNewton {
                 D = fmin(2.0 * D, 2.0);
             else if (rho < 0.25)
                 D = 0.25 * ns;
-            if (acc && ns <= kStepStop) stop = true;
+            if (acc && ns <= step_stop) stop = true;
         }
         // branch-free update: the trial Jacobian is consumed on every path,
         // so its half of the contraction is not sunk into a branch away from
@@ -238,7 +240,7 @@ struct TRNewton {
         for (int d = 0; d < 9; ++d) J[d] = acc ? Jt[d] : J[d];
         phi = acc ? phit : phi;
         have = true;
-        if (stop || phi <= rstop || it >= kMaxIter) return true;
+        if (stop || phi <= rstop || it >= max_it) return true;
         ++it;
         double g[3];
 #pragma unroll
@@ -517,326 +519,7 @@ __global__ __launch_bounds__(kGrpThreads) void k_locate_grp(LocArgs a,
     }
 }
 
-// ---------------------------------------------------------------------------
-// Matrix-core Newton.  For the pairs of one element the first contraction of
-// the element map, a(c,k,j; point) = sum_i X_c[k][j][i] h_i(r_point), is a
-// dense product (element rows x basis values of 16 points), done with the
-// 16x16x4 MFMA.  One wavefront per element: 16 pair slots, slot n owning the
-// 4 lanes n + 16 g (g = 0..3) -- the lanes that hold column n of the B
-// operand and of the result.  The element's A fragments stay in registers
-// for all its pairs.  Lane g holds, for each plane (c, k) of an M block,
-// the rows j = g + 4 w; it contracts them with h_j(s), then with h_k(t), and
-// the 4 lanes of a slot add their partial sums by a butterfly, which gives
-// bit-identical totals in all 4 lanes (IEEE addition commutes), so the 4
-// copies of the slot's Newton state stay in step.
-// ---------------------------------------------------------------------------
-typedef double dx4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ dx4 mfma16(double a, double b, dx4 c)
-{
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-// f64 16x16x4 result layout: row i, column j at lane j + 16 (i % 4),
-// component i / 4.
-__device__ __forceinline__ int mrow(int g, int v) { return 4 * v + g; }
-
-template <int N1>
-struct MShape {
-    static constexpr int JP = N1 <= 4 ? 4 : (N1 <= 8 ? 8 : 16);  // padded rows per plane
-    static constexpr int PPB = 16 / JP;                           // planes per M block
-    static constexpr int NPL = 3 * N1;                            // planes (c, k)
-    static constexpr int MB = (NPL + PPB - 1) / PPB;              // M blocks
-    static constexpr int KB = (N1 + 3) / 4;                       // K blocks (over i)
-    static constexpr int EPP = JP / 4;                            // rows per plane and lane
-    static constexpr int V = N1 * N1 * N1;
-    static constexpr int SB = (V + 15) / 16;                      // node blocks (start scan)
-};
-
-// A fragments of one element: A[mb][kb] at lane l = row + 16 q holds
-// X_c[k][j][i] for i = 4 kb + q and the (c, k, j) of row `row` of block mb.
-template <int N1>
-__device__ __forceinline__ void load_afrag(lptr<double> X, int lane,
-                                           double (&A)[MShape<N1>::MB][MShape<N1>::KB])
-{
-    using S = MShape<N1>;
-    const int row = lane & 15, q = lane >> 4;
-    const int gr = row % 4, vr = row / 4;  // inverse of mrow
-    const int p = vr / S::EPP, jj = gr + 4 * (vr % S::EPP);
-#pragma unroll
-    for (int mb = 0; mb < S::MB; ++mb) {
-        const int P = mb * S::PPB + p;
-        const int c = P / N1, k = P % N1;
-#pragma unroll
-        for (int kb = 0; kb < S::KB; ++kb) {
-            const int i = 4 * kb + q;
-            const bool ok = P < S::NPL && jj < N1 && i < N1;
-            A[mb][kb] = ok ? X[c * S::V + N1 * (jj + N1 * k) + i] : 0.0;
-        }
-    }
-}
-
-// Basis values one lane needs for its slot's trial point.
-template <int N1>
-struct LaneBasis {
-    double hrl[MShape<N1>::KB], drl[MShape<N1>::KB];   // h_i(r), i = 4 kb + g
-    double hsl[MShape<N1>::EPP], dsl[MShape<N1>::EPP]; // h_j(s), j = g + 4 w
-    double ht[N1], dt[N1];
-};
-
-template <int N1>
-__device__ __forceinline__ void lane_basis(BasisPtr<double> B, const double (&r)[3], int g,
-                                           LaneBasis<N1> &L)
-{
-    using S = MShape<N1>;
-    double h[N1], d[N1];
-    lagrange_d<N1>(B, r[0], h, d);
-#pragma unroll
-    for (int kb = 0; kb < S::KB; ++kb) {
-        double hv = 0.0, dv = 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int i = 4 * kb + q;
-            if (i < N1) {
-                hv = (g == q) ? h[i] : hv;
-                dv = (g == q) ? d[i] : dv;
-            }
-        }
-        L.hrl[kb] = hv;
-        L.drl[kb] = dv;
-    }
-    lagrange_d<N1>(B, r[1], h, d);
-#pragma unroll
-    for (int w = 0; w < S::EPP; ++w) {
-        double hv = 0.0, dv = 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int j = q + 4 * w;
-            if (j < N1) {
-                hv = (g == q) ? h[j] : hv;
-                dv = (g == q) ? d[j] : dv;
-            }
-        }
-        L.hsl[w] = hv;
-        L.dsl[w] = dv;
-    }
-    lagrange_d<N1>(B, r[2], L.ht, L.dt);
-}
-
-__device__ __forceinline__ double xor_add(double v, int m)
-{
-    return v + __shfl_xor(v, m, kWave);
-}
-
-// Map and Jacobian at the slots' trial points (all 64 lanes take part).
-template <int N1>
-__device__ __forceinline__ void mfma_geo(const double (&A)[MShape<N1>::MB][MShape<N1>::KB],
-                                         const LaneBasis<N1> &L, double (&x)[3], double (&J)[9])
-{
-    using S = MShape<N1>;
-    double v[3] = {0, 0, 0}, vr[3] = {0, 0, 0}, vs[3] = {0, 0, 0}, vt[3] = {0, 0, 0};
-#pragma unroll
-    for (int mb = 0; mb < S::MB; ++mb) {
-        dx4 ch = {0, 0, 0, 0}, cd = {0, 0, 0, 0};
-#pragma unroll
-        for (int kb = 0; kb < S::KB; ++kb) {
-            ch = mfma16(A[mb][kb], L.hrl[kb], ch);
-            cd = mfma16(A[mb][kb], L.drl[kb], cd);
-        }
-#pragma unroll
-        for (int p = 0; p < S::PPB; ++p) {
-            const int P = mb * S::PPB + p;
-            if (P < S::NPL) {
-                const int c = P / N1, k = P % N1;
-                double sa = 0.0, sd = 0.0, sb = 0.0;
-#pragma unroll
-                for (int w = 0; w < S::EPP; ++w) {
-                    const double ah = ch[p * S::EPP + w], ad = cd[p * S::EPP + w];
-                    sa = fma(ah, L.hsl[w], sa);
-                    sd = fma(ah, L.dsl[w], sd);
-                    sb = fma(ad, L.hsl[w], sb);
-                }
-                v[c] = fma(sa, L.ht[k], v[c]);
-                vt[c] = fma(sa, L.dt[k], vt[c]);
-                vs[c] = fma(sd, L.ht[k], vs[c]);
-                vr[c] = fma(sb, L.ht[k], vr[c]);
-            }
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        x[c] = xor_add(xor_add(v[c], 16), 32);
-        J[3 * c + 0] = xor_add(xor_add(vr[c], 16), 32);
-        J[3 * c + 1] = xor_add(xor_add(vs[c], 16), 32);
-        J[3 * c + 2] = xor_add(xor_add(vt[c], 16), 32);
-    }
-}
-
-// Closest node of the 16 slots' points: C = |X|^2 - 2 X . x* over the nodes
-// (rows) by MFMA; smallest value, ties to the smaller node index.
-template <int N1>
-__device__ __forceinline__ int mfma_start(lptr<double> X, int lane, const double (&xs)[3])
-{
-    using S = MShape<N1>;
-    constexpr int V = S::V;
-    const int g = lane >> 4, row = lane & 15;
-    const double b = (g < 3) ? -2.0 * xs[g] : 1.0;
-    double best = INFINITY;
-    int bn = 0;
-#pragma unroll 4
-    for (int mb = 0; mb < S::SB; ++mb) {
-        const int node = 16 * mb + row;
-        double a;
-        if (node < V) {
-            if (g < 3) {
-                a = X[g * V + node];
-            } else {
-                const double x0 = X[node], x1 = X[V + node], x2 = X[2 * V + node];
-                a = fma(x2, x2, fma(x1, x1, x0 * x0));
-            }
-        } else {
-            a = (g < 3) ? 0.0 : 1e300;  // padding rows never win
-        }
-        dx4 c = {0, 0, 0, 0};
-        c = mfma16(a, b, c);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int nd = 16 * mb + mrow(g, v);
-            if (c[v] < best) {  // nodes increase with mb and v within a lane
-                best = c[v];
-                bn = nd;
-            }
-        }
-    }
-#pragma unroll
-    for (int m = 16; m <= 32; m <<= 1) {
-        const double ob = __shfl_xor(best, m, kWave);
-        const int on = __shfl_xor(bn, m, kWave);
-        if (ob < best || (ob == best && on < bn)) {
-            best = ob;
-            bn = on;
-        }
-    }
-    return bn;
-}
-
-constexpr int kMfmaChunk = 256;  // pairs staged in LDS at a time
-
-// One wavefront per element.  LDS holds the element block (one coalesced
-// load) and, per chunk of pairs, each pair's slot, point and start node, so
-// that refilling a slot reads LDS only.
-template <int N1>
-__global__ __launch_bounds__(kWave) void k_locate_mfma(LocArgs a, const double *__restrict__ basis)
-{
-    using S = MShape<N1>;
-    constexpr int V = S::V;
-    __shared__ double sX[3 * V];
-    __shared__ double sP[3 * kMfmaChunk];
-    __shared__ int sS[kMfmaChunk], sn[kMfmaChunk];
-    const BasisPtr<double> B{as_const(basis)};
-    const int e = blockIdx.x;
-    const int beg = a.elem_off[e], end = a.elem_off[e + 1];
-    if (beg >= end) return;
-    const int lane = threadIdx.x, n = lane & 15, g = lane >> 4;
-    {
-        const double2 *src = (const double2 *)(a.geom + (long long)e * 3 * V);
-        for (int q = lane; q < 3 * V / 2; q += kWave) {
-            const double2 v = src[q];
-            sX[2 * q] = v.x;
-            sX[2 * q + 1] = v.y;
-        }
-        if ((3 * V) & 1) {
-            if (lane == 0) sX[3 * V - 1] = a.geom[(long long)e * 3 * V + 3 * V - 1];
-        }
-    }
-    __syncthreads();
-    const lptr<double> X = (lptr<double>)sX;
-    double A[S::MB][S::KB];
-    load_afrag<N1>(X, lane, A);
-    const double he = a.esize[e];
-    const double rstop = (kResidStop * he) * (kResidStop * he);
-    unsigned long long my_iters = 0;
-
-    for (int c0 = beg; c0 < end; c0 += kMfmaChunk) {
-        const int cnt = min(kMfmaChunk, end - c0);
-        for (int u = lane; u < cnt; u += kWave) {
-            const int slot = a.order[c0 + u];
-            const int tk = slot % a.M;
-            const int p = a.idx ? a.idx[tk] : tk;
-            sS[u] = slot;
-            sP[3 * u] = a.pts[3 * (long long)p];
-            sP[3 * u + 1] = a.pts[3 * (long long)p + 1];
-            sP[3 * u + 2] = a.pts[3 * (long long)p + 2];
-        }
-        __syncthreads();
-        // start nodes, 16 pairs per MFMA batch
-        for (int b0 = 0; b0 < cnt; b0 += 16) {
-            const int u = b0 + n;
-            double xs[3] = {0.0, 0.0, 0.0};
-            if (u < cnt) {
-                xs[0] = sP[3 * u];
-                xs[1] = sP[3 * u + 1];
-                xs[2] = sP[3 * u + 2];
-            }
-            const int bn = mfma_start<N1>(X, lane, xs);
-            if (u < cnt && g == 0) sn[u] = bn;
-        }
-        __syncthreads();
-
-        // Newton with slot refill
-        int u = n, next = 16;
-        int slot = 0;
-        double xs[3] = {0.0, 0.0, 0.0};
-        TRNewton t;
-        {
-            const double r0[3] = {0.0, 0.0, 0.0};
-            t.start(r0);
-        }
-        auto begin_pair = [&](int uu) {
-            slot = sS[uu];
-            xs[0] = sP[3 * uu];
-            xs[1] = sP[3 * uu + 1];
-            xs[2] = sP[3 * uu + 2];
-            double r0[3];
-            node_rst<N1>(B, sn[uu], r0);
-            t.start(r0);
-        };
-        bool active = u < cnt;
-        if (active) begin_pair(u);
-        while (__ballot(active) != 0) {
-            LaneBasis<N1> L;
-            lane_basis<N1>(B, t.rt, g, L);
-            double xt[3], Jt[9];
-            mfma_geo<N1>(A, L, xt, Jt);
-            bool done = false;
-            if (active) {
-                done = t.update(xt, Jt, xs, rstop);
-                if (done && g == 0) {
-                    my_iters += (unsigned long long)t.it;
-                    store_pair<N1>(a, B, slot, e, t, he);
-                }
-            }
-            // finished slots take the next pairs, in slot order
-            const unsigned long long fin = __ballot(done && g == 0) & 0xFFFFull;
-            if (fin) {
-                const int rank = __popcll(fin & ((1ull << n) - 1ull));
-                if (done) {
-                    u = next + rank;
-                    active = u < cnt;
-                    if (active) begin_pair(u);
-                }
-                next += __popcll(fin);
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) my_iters += __shfl_xor(my_iters, o, kWave);
-    if (lane == 0) {
-        atomicAdd(&a.stats[0], (unsigned long long)(end - beg));
-        atomicAdd(&a.stats[1], my_iters);
-    }
-}
+#include "fp_mfma.inc"
 
 // Owner selection per point (candidates are in ascending element order).
 __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ code,
@@ -943,7 +626,13 @@ static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, hip
     k_locate_grp<N1><<<(h->E + Group<N1>::G - 1) / Group<N1>::G, kGrpThreads, 0, s>>>(a, \
                                                                               h->d_basis, h->E)
 #define FP_LAUNCH_LOCATE(N1) k_locate<N1><<<h->E, kWave, 0, s>>>(a, h->d_basis)
-#define FP_LAUNCH_MFMA(N1) k_locate_mfma<N1><<<h->E, kWave, 0, s>>>(a, h->d_basis)
+#define FP_LAUNCH_MFMA(N1)                                                                \
+    do {                                                                                  \
+        if (h->precision == FP_PREC_MIXED)                                                \
+            k_locate_mfma<N1, true><<<h->E, kWave, 0, s>>>(a, h->d_basis, h->d_basis32);  \
+        else                                                                              \
+            k_locate_mfma<N1, false><<<h->E, kWave, 0, s>>>(a, h->d_basis, h->d_basis32); \
+    } while (0)
     switch (h->n1) {
         case 2: FP_LAUNCH_MFMA(2); break;
         case 3: FP_LAUNCH_MFMA(3); break;
@@ -992,10 +681,6 @@ extern "C" int findpts(fp_handle *h, int npts, const double *pts, const int *pt_
     if (!pts || !code || !el || !rst || !dist2) {
         set_error("findpts: NULL argument");
         return FP_EINVAL;
-    }
-    if (h->precision != FP_PREC_FP64) {
-        set_error("findpts: mixed precision is not available in this build");
-        return FP_ESTATE;
     }
     hipStream_t s = (hipStream_t)stream;
     int dev = 0;
