@@ -103,6 +103,9 @@ def main():
                     help="in-annulus points (1 %% more are placed outside)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after timing, run the library's plain copy kernel over this many MiB "
+                         "(reference launch for scaling hardware byte counters)")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="precision of the headline line (the other one is timed beside it)")
     args = ap.parse_args()
@@ -262,6 +265,15 @@ def main():
         }
     print(json.dumps(rec), flush=True)
     h.free()
+    if args.copy_mib > 0:
+        n = args.copy_mib << 20
+        src = torch.ones(n // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            fp.fp_copy(src, dst, stream)
+        torch.cuda.synchronize()
+        print(f"# copy kernel: {n} bytes read, {n} bytes written per launch", file=sys.stderr,
+              flush=True)
 
 
 if __name__ == "__main__":

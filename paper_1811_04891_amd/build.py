@@ -19,6 +19,9 @@ SOURCES = ["fp_util.hip", "fp_setup.hip", "fp_locate.hip", "fp_eval.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # matrix-core results in ordinary vector registers (no accumulator
+         # register copies on the Newton path)
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
 
 

@@ -254,25 +254,21 @@ struct TRNewton {
             nf += held ? 0 : 1;
         }
         if (nf == 0) return true;
-        double dl[3];
-        bool ok;
-        if (nf == 3) {
-            const double b[3] = {-F[0], -F[1], -F[2]};
-            ok = solve3(J, b, dl);
-        } else {
-            // reduced normal equations: (M J^T J M + I - M) d = -M g
-            double A[9], b[3];
+        // one solve for both cases (lanes of a wavefront differ in nf): J d = -F
+        // when all coordinates are free, else the reduced normal equations
+        // (M J^T J M + I - M) d = -M g
+        double A[9], b[3], dl[3];
 #pragma unroll
-            for (int u = 0; u < 3; ++u) {
+        for (int u = 0; u < 3; ++u) {
 #pragma unroll
-                for (int v = 0; v < 3; ++v) {
-                    const double jtj = fma(J[6 + u], J[6 + v], fma(J[3 + u], J[3 + v], J[u] * J[v]));
-                    A[3 * u + v] = m[u] * m[v] * jtj + ((u == v) ? 1.0 - m[u] : 0.0);
-                }
-                b[u] = -m[u] * g[u];
+            for (int v = 0; v < 3; ++v) {
+                const double jtj = fma(J[6 + u], J[6 + v], fma(J[3 + u], J[3 + v], J[u] * J[v]));
+                const double red = m[u] * m[v] * jtj + ((u == v) ? 1.0 - m[u] : 0.0);
+                A[3 * u + v] = (nf == 3) ? J[3 * u + v] : red;
             }
-            ok = solve3(A, b, dl);
+            b[u] = (nf == 3) ? -F[u] : -m[u] * g[u];
         }
+        const bool ok = solve3(A, b, dl);
         if (!ok) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) dl[d] = -m[d] * g[d];
