@@ -186,6 +186,67 @@ FP_API const char *fp_last_error(void);
  */
 FP_API int fp_copy(const void *src, void *dst, size_t bytes, void *stream);
 
+/*
+ * Serving layer.  Not a step of the paper's method: Section 2.1 runs one
+ * findpts (and findpts_eval per field) per Schwarz exchange over all
+ * interface points of a session; this layer serves many such calls, on many
+ * resident meshes, as they arrive.
+ *
+ *   - Meshes stay resident: fps_add_mesh registers a set-up handle and its
+ *     fields (borrowed, not copied; they must outlive the serving object).
+ *   - A request is (mesh, npts points, optional point sessions, a list of
+ *     field ids).  Its workspace (the pair arrays of findpts and the
+ *     element counters of both calls, sized for min(npts, 2^20) points per
+ *     pass) is carved from one device arena of `hbm_budget_bytes`, reserved
+ *     at fps_create.  A request is admitted when a slot (a HIP stream of the
+ *     serving object) is free and its workspace fits in the arena; until
+ *     then it waits in submission order (a later request that fits may pass
+ *     a waiting one, at most 8 times in a row).  Admitted requests run
+ *     concurrently on their slots and release slot and workspace when their
+ *     stream completes; waiting requests are then admitted.
+ *   - Results equal those of findpts + findpts_eval on the request alone
+ *     (every point's result depends only on that point and the mesh).
+ *   - Latency of a request = host time from fps_submit to the completion of
+ *     its last kernel (a host callback on its stream).
+ *
+ * All request buffers are device pointers owned by the caller: pts (npts x
+ * 3), pt_session (npts or NULL), code/el (npts), rst (npts x 3), dist2
+ * (npts), out (nfields x npts, field-major; may be NULL when nfields = 0).
+ * Inputs must be ready (their producing stream synchronised) before
+ * fps_submit; no buffer may be touched until fps_wait returns for the
+ * ticket.  Precision is the handle's (findpts_set_precision).
+ *
+ * fps_create      budget in bytes (> 0), slots in [1, 16].
+ * fps_add_mesh    fields: nfields device pointers (E x V doubles each), may
+ *                 be 0; *mesh_id receives the id (0, 1, ...).
+ * fps_submit      returns FP_ENOMEM if even a 256-point pass of the request
+ *                 exceeds the budget, FP_EINVAL for bad ids or sizes;
+ *                 *ticket receives a positive id.  Never blocks on the GPU.
+ * fps_wait        blocks until the request completed (FP_OK or its error),
+ *                 FP_EBUSY if timeout_s (>= 0; < 0 = forever) passes first.
+ *                 A ticket can be waited for once.
+ * fps_latency     p50 / p99 latency (seconds) of the requests completed
+ *                 since the last reset, and their points per second over the
+ *                 span from the first submission to the last completion;
+ *                 h_info[6] (may be NULL): completed requests, requests
+ *                 waiting, requests running, peak concurrent requests, peak
+ *                 arena bytes in use, admissions that had to wait.
+ * fps_destroy     waits for every submitted request, then frees streams and
+ *                 the arena.  Handles and fields are not freed.
+ */
+typedef struct fps fps;
+
+FP_API int fps_create(fps **s, size_t hbm_budget_bytes, int slots);
+FP_API int fps_add_mesh(fps *s, fp_handle *h, const double *const *h_fields, int nfields,
+                        int *h_mesh_id);
+FP_API int fps_submit(fps *s, int mesh_id, int npts, const double *pts, const int *pt_session,
+                      int nfields, const int *h_field_ids, int *code, int *el, double *rst,
+                      double *dist2, double *out, long long *h_ticket);
+FP_API int fps_wait(fps *s, long long ticket, double timeout_s);
+FP_API int fps_latency(fps *s, double *h_p50_s, double *h_p99_s, double *h_pts_per_s,
+                       long long *h_info, int reset);
+FP_API int fps_destroy(fps *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -187,6 +187,61 @@ static hipError_t launch_eval_kernel(int n1, int E, const EvArgs &a, const Field
     return hipGetLastError();
 }
 
+int run_eval(fp_handle *h, const Work &w, int npts, const int *code, const int *el,
+             const double *rst, int nfields, const double *const *h_fields, double *out,
+             hipStream_t s, bool timed)
+{
+    for (int start = 0; start < npts; start += w.M) {
+        const int n = (npts - start < w.M) ? npts - start : w.M;
+        hipEvent_t t0 = nullptr, t1 = nullptr, l0 = nullptr, l1 = nullptr;
+        if (timed) {
+            t0 = pool_event(h);
+            t1 = pool_event(h);
+            l0 = pool_event(h);
+            l1 = pool_event(h);
+            FP_HIP(hipEventRecord(t0, s));
+        }
+        for (int f0 = 0; f0 < nfields; f0 += kMaxEvalFields) {
+            const int nf = (nfields - f0 < kMaxEvalFields) ? nfields - f0 : kMaxEvalFields;
+            EvArgs a{};
+            a.code = code + start;
+            a.el = el + start;
+            a.rst = rst + 3 * (long long)start;
+            a.npts = n;
+            a.E = h->E;
+            a.cnt = w.ev_cnt;
+            a.off = w.ev_off;
+            a.pos = w.ev_pos;
+            a.order = w.ev_order;
+            a.out = out + (long long)f0 * npts + start;
+            a.ostride = npts;
+            a.nf = nf;
+            a.out_all = out + start;
+            a.nf_all = nfields;
+            FieldPtrs F{};
+            for (int f = 0; f < nf; ++f) F.f[f] = h_fields[f0 + f];
+            const int pb = (n + 255) / 256;
+            if (f0 == 0) {
+                FP_HIP(fill_int(w.ev_cnt, 0, (long long)h->E + 1, s));
+                k_ev_count<<<pb, 256, 0, s>>>(a);
+                FP_HIP(hipGetLastError());
+                FP_HIP(scan_exclusive(w.ev_cnt, w.ev_off, h->E, w.scan_tmp, s));
+                k_ev_scatter<<<pb, 256, 0, s>>>(a);
+                FP_HIP(hipGetLastError());
+                if (timed) FP_HIP(hipEventRecord(l0, s));
+            }
+            FP_HIP(launch_eval_kernel(h->n1, h->E, a, F, h->d_basis, s));
+        }
+        if (timed) {
+            FP_HIP(hipEventRecord(l1, s));
+            FP_HIP(hipEventRecord(t1, s));
+            h->timed.push_back(TimedPair{1, l0, l1});
+            h->timed.push_back(TimedPair{3, t0, t1});
+        }
+    }
+    return FP_OK;
+}
+
 }  // namespace fp
 
 using namespace fp;
@@ -213,57 +268,9 @@ extern "C" int findpts_eval(fp_handle *h, int npts, const int *code, const int *
             set_error("findpts_eval: NULL field pointer");
             return FP_EINVAL;
         }
-    hipStream_t s = (hipStream_t)stream;
     int dev = 0;
     FP_HIP(hipGetDevice(&dev));
     if (dev != h->device) FP_HIP(hipSetDevice(h->device));
-    for (int start = 0; start < npts; start += h->max_points) {
-        const int n = (npts - start < h->max_points) ? npts - start : h->max_points;
-        hipEvent_t t0 = nullptr, t1 = nullptr, l0 = nullptr, l1 = nullptr;
-        if (h->timing) {
-            t0 = pool_event(h);
-            t1 = pool_event(h);
-            l0 = pool_event(h);
-            l1 = pool_event(h);
-            FP_HIP(hipEventRecord(t0, s));
-        }
-        for (int f0 = 0; f0 < nfields; f0 += kMaxEvalFields) {
-            const int nf = (nfields - f0 < kMaxEvalFields) ? nfields - f0 : kMaxEvalFields;
-            EvArgs a{};
-            a.code = code + start;
-            a.el = el + start;
-            a.rst = rst + 3 * (long long)start;
-            a.npts = n;
-            a.E = h->E;
-            a.cnt = h->ev_cnt;
-            a.off = h->ev_off;
-            a.pos = h->ev_pos;
-            a.order = h->ev_order;
-            a.out = out + (long long)f0 * npts + start;
-            a.ostride = npts;
-            a.nf = nf;
-            a.out_all = out + start;
-            a.nf_all = nfields;
-            FieldPtrs F{};
-            for (int f = 0; f < nf; ++f) F.f[f] = h_fields[f0 + f];
-            const int pb = (n + 255) / 256;
-            if (f0 == 0) {
-                FP_HIP(fill_int(h->ev_cnt, 0, (long long)h->E + 1, s));
-                k_ev_count<<<pb, 256, 0, s>>>(a);
-                FP_HIP(hipGetLastError());
-                FP_HIP(scan_exclusive(h->ev_cnt, h->ev_off, h->E, h->scan_tmp, s));
-                k_ev_scatter<<<pb, 256, 0, s>>>(a);
-                FP_HIP(hipGetLastError());
-                if (h->timing) FP_HIP(hipEventRecord(l0, s));
-            }
-            FP_HIP(launch_eval_kernel(h->n1, h->E, a, F, h->d_basis, s));
-        }
-        if (h->timing) {
-            FP_HIP(hipEventRecord(l1, s));
-            FP_HIP(hipEventRecord(t1, s));
-            h->timed.push_back(TimedPair{1, l0, l1});
-            h->timed.push_back(TimedPair{3, t0, t1});
-        }
-    }
-    return FP_OK;
+    return run_eval(h, h->work, npts, code, el, rst, nfields, h_fields, out, (hipStream_t)stream,
+                    h->timing);
 }

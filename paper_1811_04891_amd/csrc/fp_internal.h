@@ -42,6 +42,35 @@ struct TimedPair {
     hipEvent_t a, b;
 };
 
+// Workspace of one findpts / findpts_eval call on one stream: M points per
+// pass, MC candidate slots per point (the longest hash-cell list), E + 1
+// element counters.  Carved from one device block; a handle owns one, the
+// serving layer carves one per admitted request from its arena.
+struct Work {
+    int M = 0, MC = 1, E = 0;
+    int *ncand = nullptr;     // M
+    int *cand_el = nullptr;   // M x MC
+    int *cand_pos = nullptr;  // M x MC, rank of the pair within its element
+    int *elem_cnt = nullptr;  // E + 1
+    int *elem_off = nullptr;  // E + 1
+    int *order = nullptr;     // M x MC pair slots grouped by element
+    double *res = nullptr;    // M x MC x 4: r, s, t, d2
+    double *res_dl = nullptr; // M x MC: delta at the candidate (if delta)
+    int *res_in = nullptr;    // M x MC: inside flag
+    int *redo = nullptr;      // M: points without an inside candidate
+    int *redo_n = nullptr;    // 1: their count
+    int *scan_tmp = nullptr;  // block sums of the device scan over E
+    int *ev_cnt = nullptr;    // E + 1
+    int *ev_off = nullptr;    // E + 1
+    int *ev_pos = nullptr;    // M
+    int *ev_order = nullptr;  // M
+};
+
+// Bytes of a workspace (256-byte aligned sub-arrays); carve() lays it out
+// from `base` (which must be 256-byte aligned).
+size_t work_bytes(int E, int MC, int M, bool delta);
+void work_carve(Work &w, char *base, int E, int MC, int M, bool delta);
+
 }  // namespace fp
 
 struct fp_handle {
@@ -68,27 +97,12 @@ struct fp_handle {
     int *cell_off = nullptr;   // ncell + 1
     int *cell_el = nullptr;    // nnz
 
-    // findpts workspace, M = max_points, MC = max_cell (>= 1)
-    int MC = 1;
-    int *ncand = nullptr;      // M
-    int *cand_el = nullptr;    // M x MC
-    int *cand_pos = nullptr;   // M x MC, rank of the pair within its element
-    int *elem_cnt = nullptr;   // E + 1
-    int *elem_off = nullptr;   // E + 1
-    int *order = nullptr;      // M x MC pair slots grouped by element
-    double *res = nullptr;     // M x MC x 4: r, s, t, d2
-    double *res_dl = nullptr;  // M x MC: delta at the candidate (if delta)
-    int *res_in = nullptr;     // M x MC: inside flag
-    int *redo = nullptr;       // M: points without an inside candidate
-    int *redo_n = nullptr;     // 1: their count
-    int *scan_tmp = nullptr;   // block sums of the device scan
+    // workspace of the handle's own calls (max_points per pass)
+    int MC = 1;                 // longest hash-cell list (>= 1)
+    fp::Work work{};
+    void *work_mem = nullptr;
+    int *scan_tmp = nullptr;    // setup's scans (cells)
     int scan_tmp_n = 0;
-
-    // findpts_eval workspace
-    int *ev_cnt = nullptr;     // E + 1
-    int *ev_off = nullptr;     // E + 1
-    int *ev_pos = nullptr;     // M
-    int *ev_order = nullptr;   // M
 
     // [pairs solved, Newton iterations, points located, axis-aligned box
     //  candidates (the hash + box candidate count of the method)]
@@ -126,11 +140,12 @@ hipError_t scan_exclusive(const int *in, int *out, int n, int *tmp,
 // Fill n ints with a value (a kernel, so that it may be graph-captured).
 hipError_t fill_int(int *p, int value, long long n, hipStream_t s);
 
-// Launchers (one per kernel family, dispatching on n1).
-hipError_t launch_locate(const fp_handle *h, int npts, const double *pts,
-                         hipStream_t s);
-hipError_t launch_eval(const fp_handle *h, int npts, const double *rst,
-                       int nf, const double *const *fields, double *out,
-                       hipStream_t s);
+// findpts / findpts_eval on a given workspace and stream (the public calls
+// pass the handle's own workspace; `timed` records the handle's events).
+int run_findpts(fp_handle *h, const Work &w, int npts, const double *pts, const int *pt_session,
+                int *code, int *el, double *rst, double *dist2, hipStream_t s, bool timed);
+int run_eval(fp_handle *h, const Work &w, int npts, const int *code, const int *el,
+             const double *rst, int nfields, const double *const *h_fields, double *out,
+             hipStream_t s, bool timed);
 
 }  // namespace fp

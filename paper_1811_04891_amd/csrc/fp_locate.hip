@@ -662,6 +662,91 @@ static void record(fp_handle *h, int phase, hipEvent_t a, hipEvent_t b)
     h->timed.push_back(TimedPair{phase, a, b});
 }
 
+namespace fp {
+
+int run_findpts(fp_handle *h, const Work &w, int npts, const double *pts, const int *pt_session,
+                int *code, int *el, double *rst, double *dist2, hipStream_t s, bool timed)
+{
+    for (int start = 0; start < npts; start += w.M) {
+        const int n = (npts - start < w.M) ? npts - start : w.M;
+        LocArgs a{};
+        a.geom = h->geom;
+        a.esize = h->esize;
+        a.bbox = h->bbox;
+        a.delta = h->delta;
+        a.esess = h->esess;
+        a.cell_off = h->cell_off;
+        a.cell_el = h->cell_el;
+        a.g = h->grid;
+        a.pts = pts + 3 * (long long)start;
+        a.psess = pt_session ? pt_session + start : nullptr;
+        a.npts = n;
+        a.M = w.M;
+        a.tol = h->tol;
+        a.ncand = w.ncand;
+        a.cand_el = w.cand_el;
+        a.cand_pos = w.cand_pos;
+        a.elem_cnt = w.elem_cnt;
+        a.elem_off = w.elem_off;
+        a.order = w.order;
+        a.res = w.res;
+        a.res_dl = h->delta ? w.res_dl : nullptr;
+        a.res_in = w.res_in;
+        a.stats = h->stats;
+
+        hipEvent_t t0 = nullptr, t1 = nullptr, l0 = nullptr, l1 = nullptr;
+        if (timed) {
+            t0 = pool_event(h);
+            t1 = pool_event(h);
+            l0 = pool_event(h);
+            l1 = pool_event(h);
+            FP_HIP(hipEventRecord(t0, s));
+        }
+        const int pb = (n + 255) / 256;
+        int *co = code + start, *eo = el + start;
+        double *ro = rst + 3 * (long long)start, *dO = dist2 + start;
+        // first pass: oriented-box candidates; points without an inside
+        // candidate go to the redo list
+        a.obb = h->obb;
+        a.redo = w.redo;
+        a.redo_n = w.redo_n;
+        FP_HIP(fill_int(w.redo_n, 0, 1, s));
+        FP_HIP(fill_int(w.elem_cnt, 0, (long long)h->E + 1, s));
+        k_cand<<<pb, 256, 0, s>>>(a);
+        FP_HIP(hipGetLastError());
+        FP_HIP(scan_exclusive(w.elem_cnt, w.elem_off, h->E, w.scan_tmp, s));
+        k_scatter<<<pb, 256, 0, s>>>(a);
+        FP_HIP(hipGetLastError());
+        if (timed) FP_HIP(hipEventRecord(l0, s));
+        FP_HIP(launch_locate_kernel(h, a, s));
+        if (timed) FP_HIP(hipEventRecord(l1, s));
+        k_select<<<pb, 256, 0, s>>>(a, co, eo, ro, dO);
+        FP_HIP(hipGetLastError());
+        // second pass over the redo list with the axis-aligned candidates
+        // only (sized on the device: kernels past the count return at once)
+        a.obb = nullptr;
+        a.idx = w.redo;
+        a.dcount = w.redo_n;
+        FP_HIP(fill_int(w.elem_cnt, 0, (long long)h->E + 1, s));
+        k_cand<<<pb, 256, 0, s>>>(a);
+        FP_HIP(hipGetLastError());
+        FP_HIP(scan_exclusive(w.elem_cnt, w.elem_off, h->E, w.scan_tmp, s));
+        k_scatter<<<pb, 256, 0, s>>>(a);
+        FP_HIP(hipGetLastError());
+        FP_HIP(launch_locate_kernel(h, a, s));
+        k_select<<<pb, 256, 0, s>>>(a, co, eo, ro, dO);
+        FP_HIP(hipGetLastError());
+        if (timed) {
+            FP_HIP(hipEventRecord(t1, s));
+            record(h, 0, l0, l1);
+            record(h, 2, t0, t1);
+        }
+    }
+    return FP_OK;
+}
+
+}  // namespace fp
+
 extern "C" int findpts(fp_handle *h, int npts, const double *pts, const int *pt_session,
                        int *code, int *el, double *rst, double *dist2, void *stream)
 {
@@ -678,84 +763,9 @@ extern "C" int findpts(fp_handle *h, int npts, const double *pts, const int *pt_
         set_error("findpts: NULL argument");
         return FP_EINVAL;
     }
-    hipStream_t s = (hipStream_t)stream;
     int dev = 0;
     FP_HIP(hipGetDevice(&dev));
     if (dev != h->device) FP_HIP(hipSetDevice(h->device));
-    for (int start = 0; start < npts; start += h->max_points) {
-        const int n = (npts - start < h->max_points) ? npts - start : h->max_points;
-        LocArgs a{};
-        a.geom = h->geom;
-        a.esize = h->esize;
-        a.bbox = h->bbox;
-        a.delta = h->delta;
-        a.esess = h->esess;
-        a.cell_off = h->cell_off;
-        a.cell_el = h->cell_el;
-        a.g = h->grid;
-        a.pts = pts + 3 * (long long)start;
-        a.psess = pt_session ? pt_session + start : nullptr;
-        a.npts = n;
-        a.M = h->max_points;
-        a.tol = h->tol;
-        a.ncand = h->ncand;
-        a.cand_el = h->cand_el;
-        a.cand_pos = h->cand_pos;
-        a.elem_cnt = h->elem_cnt;
-        a.elem_off = h->elem_off;
-        a.order = h->order;
-        a.res = h->res;
-        a.res_dl = h->delta ? h->res_dl : nullptr;
-        a.res_in = h->res_in;
-        a.stats = h->stats;
-
-        hipEvent_t t0 = nullptr, t1 = nullptr, l0 = nullptr, l1 = nullptr;
-        if (h->timing) {
-            t0 = pool_event(h);
-            t1 = pool_event(h);
-            l0 = pool_event(h);
-            l1 = pool_event(h);
-            FP_HIP(hipEventRecord(t0, s));
-        }
-        const int pb = (n + 255) / 256;
-        int *co = code + start, *eo = el + start;
-        double *ro = rst + 3 * (long long)start, *dO = dist2 + start;
-        // first pass: oriented-box candidates; points without an inside
-        // candidate go to the redo list
-        a.obb = h->obb;
-        a.redo = h->redo;
-        a.redo_n = h->redo_n;
-        FP_HIP(fill_int(h->redo_n, 0, 1, s));
-        FP_HIP(fill_int(h->elem_cnt, 0, (long long)h->E + 1, s));
-        k_cand<<<pb, 256, 0, s>>>(a);
-        FP_HIP(hipGetLastError());
-        FP_HIP(scan_exclusive(h->elem_cnt, h->elem_off, h->E, h->scan_tmp, s));
-        k_scatter<<<pb, 256, 0, s>>>(a);
-        FP_HIP(hipGetLastError());
-        if (h->timing) FP_HIP(hipEventRecord(l0, s));
-        FP_HIP(launch_locate_kernel(h, a, s));
-        if (h->timing) FP_HIP(hipEventRecord(l1, s));
-        k_select<<<pb, 256, 0, s>>>(a, co, eo, ro, dO);
-        FP_HIP(hipGetLastError());
-        // second pass over the redo list with the axis-aligned candidates
-        // only (sized on the device: kernels past the count return at once)
-        a.obb = nullptr;
-        a.idx = h->redo;
-        a.dcount = h->redo_n;
-        FP_HIP(fill_int(h->elem_cnt, 0, (long long)h->E + 1, s));
-        k_cand<<<pb, 256, 0, s>>>(a);
-        FP_HIP(hipGetLastError());
-        FP_HIP(scan_exclusive(h->elem_cnt, h->elem_off, h->E, h->scan_tmp, s));
-        k_scatter<<<pb, 256, 0, s>>>(a);
-        FP_HIP(hipGetLastError());
-        FP_HIP(launch_locate_kernel(h, a, s));
-        k_select<<<pb, 256, 0, s>>>(a, co, eo, ro, dO);
-        FP_HIP(hipGetLastError());
-        if (h->timing) {
-            FP_HIP(hipEventRecord(t1, s));
-            record(h, 0, l0, l1);
-            record(h, 2, t0, t1);
-        }
-    }
-    return FP_OK;
+    return run_findpts(h, h->work, npts, pts, pt_session, code, el, rst, dist2,
+                       (hipStream_t)stream, h->timing);
 }

@@ -415,16 +415,75 @@ __global__ __launch_bounds__(256) void k_hash_sort(const int *__restrict__ off,
 }  // namespace fp
 
 // ---------------------------------------------------------------------------
+// Workspace layout.
+// ---------------------------------------------------------------------------
+namespace fp {
+
+namespace {
+struct Layout {
+    size_t off = 0;
+    char *base = nullptr;
+    template <class T>
+    T *take(size_t count)
+    {
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += ((sizeof(T) * (count ? count : 1) + 255) / 256) * 256;
+        return p;
+    }
+};
+
+void lay_out(Layout &L, Work &w, int E, int MC, int M, bool delta)
+{
+    const size_t m = (size_t)M, mc = (size_t)MC, e1 = (size_t)E + 1;
+    w.M = M;
+    w.MC = MC;
+    w.E = E;
+    w.ncand = L.take<int>(m);
+    w.cand_el = L.take<int>(m * mc);
+    w.cand_pos = L.take<int>(m * mc);
+    w.elem_cnt = L.take<int>(e1);
+    w.elem_off = L.take<int>(e1);
+    w.order = L.take<int>(m * mc);
+    w.res = L.take<double>(m * mc * 4);
+    w.res_dl = delta ? L.take<double>(m * mc) : nullptr;
+    w.res_in = L.take<int>(m * mc);
+    w.redo = L.take<int>(m);
+    w.redo_n = L.take<int>(1);
+    w.scan_tmp = L.take<int>((size_t)scan_tmp_size((long long)E + 1));
+    w.ev_cnt = L.take<int>(e1);
+    w.ev_off = L.take<int>(e1);
+    w.ev_pos = L.take<int>(m);
+    w.ev_order = L.take<int>(m);
+}
+}  // namespace
+
+size_t work_bytes(int E, int MC, int M, bool delta)
+{
+    Layout L;
+    Work w;
+    lay_out(L, w, E, MC, M, delta);
+    return L.off;
+}
+
+void work_carve(Work &w, char *base, int E, int MC, int M, bool delta)
+{
+    Layout L;
+    L.base = base;
+    lay_out(L, w, E, MC, M, delta);
+}
+
+}  // namespace fp
+
+// ---------------------------------------------------------------------------
 // Handle lifetime.
 // ---------------------------------------------------------------------------
 using namespace fp;
 
 static void release(fp_handle *h)
 {
-    void *ptrs[] = {h->d_basis, h->d_basis32, h->geom, h->geom32, h->esize, h->bbox, h->obb, h->esess, h->delta,
-                    h->cell_off, h->cell_el, h->ncand, h->cand_el, h->cand_pos,
-                    h->elem_cnt, h->elem_off, h->order, h->res, h->res_dl, h->res_in, h->redo, h->redo_n,
-                    h->scan_tmp, h->ev_cnt, h->ev_off, h->ev_pos, h->ev_order, h->stats};
+    void *ptrs[] = {h->d_basis, h->d_basis32, h->geom, h->geom32, h->esize, h->bbox, h->obb,
+                    h->esess, h->delta, h->cell_off, h->cell_el, h->work_mem, h->scan_tmp,
+                    h->stats};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &t : h->timed) {
@@ -611,27 +670,17 @@ extern "C" int findpts_setup(fp_handle **out, const double *x, const double *y,
     h->MC = std::max(1, maxlen);
 
     // workspace
-    const size_t M = (size_t)max_points, MC = (size_t)h->MC;
-    if ((double)M * (double)MC >= 2147483647.0) {
+    if ((double)max_points * (double)h->MC >= 2147483647.0) {
         release(h);
         set_error("findpts_setup: max_points x longest cell list exceeds 2^31; lower max_points");
         return FP_ERANGE;
     }
-    FP_HIP_H(dalloc(h, &h->ncand, M));
-    FP_HIP_H(dalloc(h, &h->cand_el, M * MC));
-    FP_HIP_H(dalloc(h, &h->cand_pos, M * MC));
-    FP_HIP_H(dalloc(h, &h->elem_cnt, (size_t)E + 1));
-    FP_HIP_H(dalloc(h, &h->elem_off, (size_t)E + 1));
-    FP_HIP_H(dalloc(h, &h->order, M * MC));
-    FP_HIP_H(dalloc(h, &h->res, M * MC * 4));
-    FP_HIP_H(dalloc(h, &h->res_in, M * MC));
-    FP_HIP_H(dalloc(h, &h->redo, M));
-    FP_HIP_H(dalloc(h, &h->redo_n, 1));
-    if (h->delta) FP_HIP_H(dalloc(h, &h->res_dl, M * MC));
-    FP_HIP_H(dalloc(h, &h->ev_cnt, (size_t)E + 1));
-    FP_HIP_H(dalloc(h, &h->ev_off, (size_t)E + 1));
-    FP_HIP_H(dalloc(h, &h->ev_pos, M));
-    FP_HIP_H(dalloc(h, &h->ev_order, M));
+    {
+        const size_t wb = work_bytes(E, h->MC, max_points, h->delta != nullptr);
+        FP_HIP_H(hipMalloc(&h->work_mem, wb));
+        h->bytes += wb;
+        work_carve(h->work, (char *)h->work_mem, E, h->MC, max_points, h->delta != nullptr);
+    }
     FP_HIP_H(hipStreamSynchronize(s));
     *out = h;
     return FP_OK;

@@ -26,7 +26,9 @@ FP_PREC_FP64, FP_PREC_MIXED = 0, 1
 SYMBOLS = ("findpts_setup", "findpts", "findpts_eval", "findpts_set_precision",
            "findpts_stats", "findpts_timing", "findpts_timing_read",
            "findpts_get_bbox", "findpts_get_hash", "findpts_get_cells",
-           "findpts_footprint", "findpts_free", "fp_last_error", "fp_copy")
+           "findpts_footprint", "findpts_free", "fp_last_error", "fp_copy",
+           "fps_create", "fps_add_mesh", "fps_submit", "fps_wait", "fps_latency",
+           "fps_destroy")
 
 
 class FindptsError(RuntimeError):
@@ -64,6 +66,12 @@ def lib():
     L.fp_last_error.restype = C.c_char_p
     L.fp_last_error.argtypes = []
     L.fp_copy.argtypes = [vp, vp, C.c_size_t, vp]
+    L.fps_create.argtypes = [C.POINTER(vp), C.c_size_t, C.c_int]
+    L.fps_add_mesh.argtypes = [vp, vp, C.POINTER(vp), C.c_int, ip]
+    L.fps_submit.argtypes = [vp, C.c_int, C.c_int, vp, vp, C.c_int, ip, vp, vp, vp, vp, vp, llp]
+    L.fps_wait.argtypes = [vp, C.c_longlong, C.c_double]
+    L.fps_latency.argtypes = [vp, dp, dp, dp, llp, C.c_int]
+    L.fps_destroy.argtypes = [vp]
     for name in SYMBOLS:
         if name != "fp_last_error":
             getattr(L, name).restype = C.c_int
@@ -237,3 +245,91 @@ def fp_copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
         raise ValueError("dst too small")
     _check(lib().fp_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
                          nbytes, _stream(stream)), "fp_copy")
+
+
+class Request:
+    """Outputs of one served request (valid once Server.wait returned)."""
+
+    def __init__(self, ticket: int, code, el, rst, dist2, out, keep):
+        self.ticket, self.code, self.el, self.rst, self.dist2, self.out = (
+            ticket, code, el, rst, dist2, out)
+        self._keep = keep  # inputs stay alive until the request completed
+
+
+class Server:
+    """The serving layer (fps_*): resident meshes, HBM-budgeted admission,
+    `slots` concurrent HIP streams, p50/p99 latency.  Keeps the registered
+    handles and fields alive for its own lifetime."""
+
+    def __init__(self, hbm_budget_bytes: int, slots: int = 4):
+        p = C.c_void_p()
+        _check(lib().fps_create(C.byref(p), int(hbm_budget_bytes), int(slots)), "fps_create")
+        self.ptr = p
+        self._meshes = []
+
+    def add_mesh(self, h: Handle, fields: Sequence[torch.Tensor] = ()) -> int:
+        for i, f in enumerate(fields):
+            _ptr(f, torch.float64, f"fields[{i}]", h.E * h.V)
+        arr = (C.c_void_p * max(1, len(fields)))(*[f.data_ptr() for f in fields])
+        mid = C.c_int()
+        _check(lib().fps_add_mesh(self.ptr, h.ptr, arr, len(fields), C.byref(mid)),
+               "fps_add_mesh")
+        self._meshes.append((h, list(fields)))
+        return mid.value
+
+    def submit(self, mesh_id: int, pts: torch.Tensor, field_ids: Sequence[int] = (),
+               pt_session: Optional[torch.Tensor] = None, out=None) -> Request:
+        """Queue a request; `pts` must be ready (its stream synchronised)."""
+        P = pts.shape[0] if pts.dim() == 2 else pts.numel() // 3
+        dev = pts.device
+        nf = len(field_ids)
+        if out is None:
+            code = torch.empty(P, dtype=torch.int32, device=dev)
+            el = torch.empty(P, dtype=torch.int32, device=dev)
+            rst = torch.empty((P, 3), dtype=torch.float64, device=dev)
+            d2 = torch.empty(P, dtype=torch.float64, device=dev)
+            vals = torch.empty((nf, P), dtype=torch.float64, device=dev) if nf else None
+        else:
+            code, el, rst, d2, vals = out
+        ids = (C.c_int * max(1, nf))(*[int(i) for i in field_ids])
+        t = C.c_longlong()
+        _check(lib().fps_submit(self.ptr, int(mesh_id), int(P),
+                                _ptr(pts, torch.float64, "pts", 3 * P),
+                                _ptr(pt_session, torch.int32, "pt_session", P), nf, ids,
+                                _ptr(code, torch.int32, "code", P), _ptr(el, torch.int32, "el", P),
+                                _ptr(rst, torch.float64, "rst", 3 * P),
+                                _ptr(d2, torch.float64, "dist2", P),
+                                _ptr(vals, torch.float64, "out", nf * P) if nf else None,
+                                C.byref(t)), "fps_submit")
+        return Request(t.value, code, el, rst, d2, vals, (pts, pt_session))
+
+    def wait(self, req, timeout_s: float = -1.0) -> int:
+        """FP_OK when done, FP_EBUSY on timeout; raises on a failed request."""
+        ticket = req.ticket if isinstance(req, Request) else int(req)
+        rc = lib().fps_wait(self.ptr, C.c_longlong(ticket), float(timeout_s))
+        if rc == FP_EBUSY:
+            return rc
+        _check(rc, "fps_wait")
+        return rc
+
+    def latency(self, reset: bool = False) -> dict:
+        p50, p99, rate = C.c_double(), C.c_double(), C.c_double()
+        info = (C.c_longlong * 6)()
+        _check(lib().fps_latency(self.ptr, C.byref(p50), C.byref(p99), C.byref(rate), info,
+                                 int(reset)), "fps_latency")
+        return {"p50_s": p50.value, "p99_s": p99.value, "points_per_s": rate.value,
+                "completed": info[0], "waiting": info[1], "running": info[2],
+                "peak_concurrent": info[3], "peak_arena_bytes": info[4],
+                "waited_admissions": info[5]}
+
+    def destroy(self):
+        if self.ptr is not None and self.ptr.value:
+            _check(lib().fps_destroy(self.ptr), "fps_destroy")
+        self.ptr = None
+        self._meshes = []
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass

@@ -67,3 +67,21 @@ def test_binding_rejects_cpu_tensors():
     x = torch.zeros(27, dtype=torch.float64)
     with pytest.raises(ValueError):
         fp.findpts_setup(x, x, x, 2)
+
+
+def test_serving_argument_checks_without_gpu():
+    L = fp.lib()
+    s = C.c_void_p()
+    assert L.fps_create(None, 1 << 20, 2) == fp.FP_EINVAL
+    assert L.fps_create(C.byref(s), 0, 2) == fp.FP_EINVAL
+    assert L.fps_create(C.byref(s), 1 << 20, 0) == fp.FP_EINVAL
+    assert L.fps_create(C.byref(s), 1 << 20, 17) == fp.FP_EINVAL
+    mid = C.c_int()
+    assert L.fps_add_mesh(None, None, None, 0, C.byref(mid)) == fp.FP_EINVAL
+    t = C.c_longlong()
+    assert L.fps_submit(None, 0, 1, None, None, 0, None, None, None, None, None, None,
+                        C.byref(t)) == fp.FP_EINVAL
+    assert L.fps_wait(None, 1, 0.0) == fp.FP_EINVAL
+    d = C.c_double()
+    assert L.fps_latency(None, C.byref(d), C.byref(d), C.byref(d), None, 0) == fp.FP_EINVAL
+    assert L.fps_destroy(None) == fp.FP_OK

@@ -30,3 +30,9 @@ from .meshes import (  # noqa: F401
     poly_fields,
     ref_poly_fields,
 )
+from .serving import (  # noqa: F401
+    ServedMesh,
+    serving_meshes,
+    serving_requests,
+    serving_points,
+)
