@@ -6,12 +6,17 @@ cylinder-in-box annulus, 16,384 curved hexahedra of order 7 (64 azimuthal x
 positions), 1,010,000 query points (1e6 area-uniform in the annulus plus 1 %
 outside it), 4 float64 fields given as random polynomials of total degree 7.
 All inputs are synthetic, seeded, and resident in HBM before timing starts.
+Both precisions are timed; --precision picks the headline one.
 
 Prints one JSON line.  Besides the throughput it reports:
-  roofline      the Newton (locate) kernel, bound by float64 vector ALU:
-                algorithmic flops per launch / its mean duration (HIP events
-                recorded by the library on the launch stream) vs 78.6 TFLOP/s
+  roofline      the Newton (locate) kernel, FP64: algorithmic flops per launch
+                / its mean duration (HIP events recorded by the library on the
+                launch stream) vs 78.6 TFLOP/s; HBM traffic from the committed
+                hardware-counter summary when it was taken on this source
   cpu_baseline  the CPU oracle timed on a bounded sample of the same points
+  serving       a stream of requests on 16 resident meshes through the
+                serving layer: saturated throughput and p50/p99 latency at
+                0.5, 0.8 and 0.95 of the saturated request rate
 """
 import argparse
 import hashlib
@@ -77,11 +82,12 @@ def cpu_baseline(mesh, pts, fields, target_s=10.0):
     nthreads = len(os.sched_getaffinity(0))
     cores = oracle.threads(nthreads)
     p = pts.cpu().numpy()
-    probe = p[: 4000]
+    # size the sample from a probe large enough to keep every thread busy
+    probe_n = min(len(p), 50_000)
     t = time.perf_counter()
-    om.findpts(probe, nthreads=nthreads)
+    om.findpts(p[:probe_n], nthreads=nthreads)
     dt = time.perf_counter() - t
-    n = int(min(len(p), max(4000, 4000 * target_s / max(dt, 1e-3))))
+    n = int(min(len(p), max(probe_n, probe_n * target_s / max(dt, 1e-3))))
     sample = p[:n]
     hf = [f.cpu().numpy() for f in fields]
     t = time.perf_counter()
@@ -92,6 +98,95 @@ def cpu_baseline(mesh, pts, fields, target_s=10.0):
     K = om.last_stats[1] / max(om.last_stats[0], 1)
     return {"n": n, "seconds": t_loc, "cores": cores, "c": c, "K": K, "om": om,
             "sample_code": code}
+
+
+def serving_bench(fp, w, dev, precision, n_req, n_warm, slots=4, seed=40):
+    """Serving stream: 16 resident meshes (E log-uniform in 500..50,000,
+    N in {5, 7, 9}, 5 fields each), requests of 1e3..1e6 points (log-uniform)
+    with 1..5 fields, Poisson arrivals at 0.5, 0.8 and 0.95 of the saturated
+    request rate.  Returns p50/p99 latency per arrival rate."""
+    import numpy as np
+    import torch
+
+    t0 = time.perf_counter()
+    ms = w.serving_meshes(count=16, device=dev)
+    handles = []
+    for m in ms:
+        md = m.mesh
+        handles.append(fp.findpts_setup(md.x, md.y, md.z, md.N, tol=1e-12, max_points=4096,
+                                        precision=precision))
+    torch.cuda.synchronize()
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(min(0.8 * free, 64 << 30))
+    srv = fp.Server(budget, slots=slots)
+    ids = [srv.add_mesh(h, m.fields) for h, m in zip(handles, ms)]
+    rq = w.serving_requests(n_warm + n_req, len(ms), seed=seed)
+    pts, outs = [], []
+    for r in rq:
+        p = w.serving_points(ms[r["mesh"]].kind, r["P"], r["seed"], dev)
+        P, nf = r["P"], len(r["field_ids"])
+        pts.append(p)
+        outs.append((torch.empty(P, dtype=torch.int32, device=dev),
+                     torch.empty(P, dtype=torch.int32, device=dev),
+                     torch.empty((P, 3), dtype=torch.float64, device=dev),
+                     torch.empty(P, dtype=torch.float64, device=dev),
+                     torch.empty((nf, P), dtype=torch.float64, device=dev)))
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    mean_p = float(np.mean([r["P"] for r in rq[n_warm:]]))
+    print(f"# serving: {len(ms)} meshes, E total {sum(m.mesh.E for m in ms)}, "
+          f"{len(rq)} requests, mean {mean_p:.0f} points, generated in {gen_s:.1f} s",
+          file=sys.stderr, flush=True)
+
+    def run(rate):
+        # warm-up requests back to back, then the measured ones at `rate`
+        # requests/s (None: all at once)
+        for i in range(n_warm):
+            srv.wait(srv.submit(ids[rq[i]["mesh"]], pts[i], rq[i]["field_ids"], out=outs[i]))
+        srv.latency(reset=True)
+        t = time.perf_counter()
+        tickets = []
+        for i in range(n_warm, len(rq)):
+            if rate is not None:
+                t += rq[i]["gap"] / rate
+                while True:
+                    d = t - time.perf_counter()
+                    if d <= 0:
+                        break
+                    time.sleep(min(d, 2e-4) if d > 5e-4 else 0)
+            tickets.append(srv.submit(ids[rq[i]["mesh"]], pts[i], rq[i]["field_ids"],
+                                      out=outs[i]))
+        for q in tickets:
+            srv.wait(q)
+        return srv.latency(reset=True)
+
+    sat = run(None)
+    R = sat["points_per_s"] / mean_p
+    levels = []
+    for frac in (0.5, 0.8, 0.95):
+        lat = run(frac * R)
+        levels.append({"rate_frac": frac, "requests_per_s": frac * R,
+                       "p50_ms": lat["p50_s"] * 1e3, "p99_ms": lat["p99_s"] * 1e3,
+                       "points_per_s": lat["points_per_s"],
+                       "peak_concurrent": lat["peak_concurrent"]})
+        print(f"# serving at {frac:.2f} R: p50 {lat['p50_s'] * 1e3:.2f} ms, "
+              f"p99 {lat['p99_s'] * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    srv.destroy()
+    for h in handles:
+        h.free()
+    return {
+        "workload": "16 resident meshes (even: sine-perturbed cubes, odd: annuli), E "
+                    f"{min(m.mesh.E for m in ms)}..{max(m.mesh.E for m in ms)}, N in {{5,7,9}}, "
+                    f"5 fields each; {n_req} measured requests (+{n_warm} warm-up) of "
+                    "1e3..1e6 points log-uniform, 1..5 fields, Poisson arrivals",
+        "precision": "mixed" if precision == fp.FP_PREC_MIXED else "fp64",
+        "slots": slots, "hbm_budget_bytes": budget,
+        "mean_points_per_request": mean_p,
+        "saturated": {"points_per_s": sat["points_per_s"], "requests_per_s": R,
+                      "p50_ms": sat["p50_s"] * 1e3, "p99_ms": sat["p99_s"] * 1e3,
+                      "peak_concurrent": sat["peak_concurrent"]},
+        "poisson": levels,
+    }
 
 
 def main():
@@ -106,6 +201,9 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after timing, run the library's plain copy kernel over this many MiB "
                          "(reference launch for scaling hardware byte counters)")
+    ap.add_argument("--serving-requests", type=int, default=1000,
+                    help="measured requests of the serving stream (0 = skip it)")
+    ap.add_argument("--serving-warmup", type=int, default=50)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="precision of the headline line (the other one is timed beside it)")
     args = ap.parse_args()
@@ -263,8 +361,13 @@ def main():
             "method_candidates_per_point": cb["c"],
             "method_newton_iters_per_candidate": cb["K"],
         }
-    print(json.dumps(rec), flush=True)
     h.free()
+    if args.serving_requests > 0:
+        sv = serving_bench(fp, w, dev, head, args.serving_requests, args.serving_warmup)
+        rec["serving"] = sv
+        mid = sv["poisson"][1]
+        rec["p50_ms"], rec["p99_ms"] = mid["p50_ms"], mid["p99_ms"]
+    print(json.dumps(rec), flush=True)
     if args.copy_mib > 0:
         n = args.copy_mib << 20
         src = torch.ones(n // 8, dtype=torch.float64, device=dev)

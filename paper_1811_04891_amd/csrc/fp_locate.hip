@@ -11,8 +11,11 @@
 //              (ascending element ids) and each pair's rank in its element
 //   scan       pair counts per element -> element offsets
 //   k_scatter  pair slots grouped by element
-//   k_locate   one 64-lane wavefront per element; lanes = pairs of that
-//              element; node data read once per wave through scalar loads
+//   k_locate_mfma  (orders 1..7) one wavefront per element, element block in
+//              LDS, map and Jacobian of 16 pairs at a time on the matrix
+//              cores (fp_mfma.inc)
+//   k_locate   (orders 8..15) one wavefront per element, lanes = pairs of
+//              that element, node rows through scalar loads
 //   k_select   per point: classification and owner rule, caller's order
 #include <cmath>
 
@@ -339,8 +342,9 @@ __device__ __forceinline__ void store_pair(const LocArgs &a, BasisPtr<double> B,
     }
 }
 
-// One 64-lane wavefront per element, node rows from the scalar cache (used
-// for orders above 9, whose element block does not fit the LDS budget).
+// One 64-lane wavefront per element, lanes over its pairs, node rows from the
+// scalar cache (orders 8 and above, whose matrix-core fragments would not fit
+// in registers).
 template <int N1>
 __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__restrict__ basis)
 {
@@ -399,119 +403,6 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
     if (threadIdx.x == 0) {
         atomicAdd(&a.stats[0], (unsigned long long)(end - beg));
         atomicAdd(&a.stats[1], my_iters);
-    }
-}
-
-// Element groups staged in LDS.  A 256-thread block owns G consecutive
-// elements and every (point, element) pair of them (contiguous in the
-// element-grouped order).  After staging the G element blocks (each padded
-// by 16 bytes so that lanes reading different elements hit different LDS
-// banks), the block first finds every pair's closest node (full-width
-// scans), then runs Newton with lane refill: a lane that finishes its pair
-// takes the next unstarted pair of the group, so lanes stay busy while
-// iteration counts differ.
-constexpr int kGrpThreads = 256;
-
-template <int N1>
-struct Group {
-    static constexpr int V = N1 * N1 * N1;
-    static constexpr int stride = 3 * V + 2;  // doubles per staged element
-    static constexpr int G = (3 * V * 8 <= 6 * 1024) ? 8 : (3 * V * 8 <= 12 * 1024 ? 4 : 2);
-    static constexpr int lds_bytes = G * stride * 8;
-};
-
-template <int N1>
-__global__ __launch_bounds__(kGrpThreads) void k_locate_grp(LocArgs a,
-                                                          const double *__restrict__ basis,
-                                                          int E)
-{
-    using Gr = Group<N1>;
-    constexpr int V = Gr::V, G = Gr::G, S = Gr::stride;
-    __shared__ double sX[G * S];
-    __shared__ int next;
-    const BasisPtr<double> B{as_const(basis)};
-    const int e0 = blockIdx.x * G;
-    const int ne = min(G, E - e0);
-    const int pb = a.elem_off[e0], pe = a.elem_off[e0 + ne];
-    const int count = pe - pb;
-    if (count <= 0) return;  // uniform across the block
-    // stage the elements that have pairs (others are never read)
-    for (int g = 0; g < ne; ++g) {
-        if (a.elem_off[e0 + g + 1] == a.elem_off[e0 + g]) continue;
-        const double2 *src = (const double2 *)(a.geom + (long long)(e0 + g) * 3 * V);
-        double *dst = sX + g * S;
-        for (int q = threadIdx.x; q < 3 * V / 2; q += kGrpThreads) {
-            const double2 v = src[q];
-            dst[2 * q] = v.x;
-            dst[2 * q + 1] = v.y;
-        }
-        if ((3 * V) & 1) {
-            if (threadIdx.x == 0) dst[3 * V - 1] = a.geom[(long long)(e0 + g) * 3 * V + 3 * V - 1];
-        }
-    }
-    if (threadIdx.x == 0) next = kGrpThreads;
-    __syncthreads();
-
-    // closest node of every pair (stored in cand_pos, free after the scatter)
-    for (int u = threadIdx.x; u < count; u += kGrpThreads) {
-        const int slot = a.order[pb + u];
-        const int tk = slot % a.M;
-        const int p = a.idx ? a.idx[tk] : tk;
-        const int g = a.cand_el[slot] - e0;
-        const double x0 = a.pts[3 * (long long)p], x1 = a.pts[3 * (long long)p + 1],
-                     x2 = a.pts[3 * (long long)p + 2];
-        lptr<double> X = (lptr<double>)(sX + g * S);
-        double best = INFINITY;
-        int bq = 0;
-#pragma unroll 8
-        for (int n = 0; n < V; ++n) {
-            const double dx = X[n] - x0, dy = X[V + n] - x1, dz = X[2 * V + n] - x2;
-            const double d = fma(dz, dz, fma(dy, dy, dx * dx));
-            if (d < best) {
-                best = d;
-                bq = n;
-            }
-        }
-        a.cand_pos[slot] = bq;
-    }
-    __syncthreads();
-
-    // Newton with lane refill
-    unsigned long long my_iters = 0;
-    int u = threadIdx.x;
-    int slot = 0, g = 0;
-    double xs[3] = {0.0, 0.0, 0.0}, he = 0.0, rstop = 0.0;
-    TRNewton t;
-    auto begin_pair = [&](int uu) {
-        slot = a.order[pb + uu];
-        const int tk = slot % a.M;
-        const int p = a.idx ? a.idx[tk] : tk;
-        g = a.cand_el[slot] - e0;
-        xs[0] = a.pts[3 * (long long)p];
-        xs[1] = a.pts[3 * (long long)p + 1];
-        xs[2] = a.pts[3 * (long long)p + 2];
-        he = a.esize[e0 + g];
-        rstop = (kResidStop * he) * (kResidStop * he);
-        double r0[3];
-        node_rst<N1>(B, a.cand_pos[slot], r0);
-        t.start(r0);
-    };
-    if (u < count) begin_pair(u);
-    while (u < count) {
-        double xt[3], Jt[9];
-        geo_eval_lds<N1>((lptr<double>)(sX + g * S), B, t.rt, xt, Jt);
-        if (t.update(xt, Jt, xs, rstop)) {
-            my_iters += (unsigned long long)t.it;
-            store_pair<N1>(a, B, slot, e0 + g, t, he);
-            u = atomicAdd(&next, 1);
-            if (u < count) begin_pair(u);
-        }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) my_iters += __shfl_xor(my_iters, o, kWave);
-    if ((threadIdx.x & (kWave - 1)) == 0) {
-        atomicAdd(&a.stats[1], my_iters);
-        if (threadIdx.x == 0) atomicAdd(&a.stats[0], (unsigned long long)count);
     }
 }
 
@@ -618,9 +509,6 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
 
 static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, hipStream_t s)
 {
-#define FP_LAUNCH_GRP(N1)                                                                 \
-    k_locate_grp<N1><<<(h->E + Group<N1>::G - 1) / Group<N1>::G, kGrpThreads, 0, s>>>(a, \
-                                                                              h->d_basis, h->E)
 #define FP_LAUNCH_LOCATE(N1) k_locate<N1><<<h->E, kWave, 0, s>>>(a, h->d_basis)
 #define FP_LAUNCH_MFMA(N1)                                                                \
     do {                                                                                  \
@@ -637,8 +525,8 @@ static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, hip
         case 6: FP_LAUNCH_MFMA(6); break;
         case 7: FP_LAUNCH_MFMA(7); break;
         case 8: FP_LAUNCH_MFMA(8); break;
-        case 9: FP_LAUNCH_GRP(9); break;
-        case 10: FP_LAUNCH_GRP(10); break;
+        case 9: FP_LAUNCH_LOCATE(9); break;
+        case 10: FP_LAUNCH_LOCATE(10); break;
         case 11: FP_LAUNCH_LOCATE(11); break;
         case 12: FP_LAUNCH_LOCATE(12); break;
         case 13: FP_LAUNCH_LOCATE(13); break;
@@ -647,7 +535,6 @@ static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, hip
         case 16: FP_LAUNCH_LOCATE(16); break;
         default: return hipErrorInvalidValue;
     }
-#undef FP_LAUNCH_GRP
 #undef FP_LAUNCH_LOCATE
 #undef FP_LAUNCH_MFMA
     return hipGetLastError();
