@@ -6,6 +6,7 @@
 
 #include "fp_basis.h"
 #include "fp_internal.h"
+#include "fp_mfma.h"
 
 namespace fp {
 
@@ -146,19 +147,121 @@ __global__ __launch_bounds__(kEvThreads) void k_eval_grp(EvArgs a, FieldPtrs F,
     }
 }
 
+// Interpolation on the matrix cores (orders 1..7): one wavefront per element,
+// its points in batches of 16.  For field f the first contraction
+// a_f(k, j; point) = sum_i F_f[k][j][i] h_i(r_point) is a dense product of the
+// field's rows (n1^2 x n1) with the basis values of 16 points, one
+// v_mfma_f64_16x16x4f64 per 16 rows and 4 i-values; the field's A fragments
+// stay in registers for all points of the element.  Lane n + 16 g supplies
+// h_i(r) for i = 4 kb + g of point n, contracts its rows j = g + 4 w with
+// h_j(s) and every plane k with h_k(t), and the 4 lanes of point n add their
+// partial sums (same order in all 4: the total is bit-identical).
+constexpr int kEvFieldsPerPass = 4;
+
+template <int N1>
+__global__ __launch_bounds__(kWave) void k_eval_mfma(EvArgs a, FieldPtrs F,
+                                                     const double *__restrict__ basis)
+{
+    using S = MShape<N1>;
+    constexpr int V = N1 * N1 * N1;
+    constexpr int MBF = (N1 + S::PPB - 1) / S::PPB;  // M blocks per field (planes k)
+    constexpr int NF = kEvFieldsPerPass;
+    const BasisPtr<double> B{as_const(basis)};
+    const int e = blockIdx.x;
+    const int beg = a.off[e], end = a.off[e + 1];
+    if (beg >= end) return;
+    const int lane = threadIdx.x, n = lane & 15, g = lane >> 4;
+    // A fragment coordinates of this lane: row -> plane p, row jj; column i
+    const int row = lane & 15, q = lane >> 4;
+    const int gr = MF<double>::grp(row), vr = MF<double>::comp(row);
+    const int pr = vr / S::EPP, jj = gr + 4 * (vr % S::EPP);
+    for (int f0 = 0; f0 < a.nf; f0 += NF) {
+        double A[NF][MBF][S::KB];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const double *src = (f0 + f < a.nf) ? F.f[f0 + f] + (long long)e * V : nullptr;
+#pragma unroll
+            for (int mb = 0; mb < MBF; ++mb) {
+                const int k = mb * S::PPB + pr;
+#pragma unroll
+                for (int kb = 0; kb < S::KB; ++kb) {
+                    const int i = 4 * kb + q;
+                    const bool ok = src && k < N1 && jj < N1 && i < N1;
+                    A[f][mb][kb] = ok ? src[N1 * (jj + N1 * k) + i] : 0.0;
+                }
+            }
+        }
+        for (int b0 = beg; b0 < end; b0 += 16) {
+            const int u = b0 + n;
+            const bool act = u < end;
+            const int p = a.order[act ? u : beg];
+            double hr[N1], hs[N1], ht[N1];
+            lagrange<N1>(B, a.rst[3 * (long long)p], hr);
+            lagrange<N1>(B, a.rst[3 * (long long)p + 1], hs);
+            lagrange<N1>(B, a.rst[3 * (long long)p + 2], ht);
+            double hrl[S::KB], hsl[S::EPP];
+#pragma unroll
+            for (int w = 0; w < S::KB; ++w) {
+                double vr_ = 0.0, vs_ = 0.0;
+#pragma unroll
+                for (int gg = 0; gg < 4; ++gg) {
+                    const int i = gg + 4 * w;
+                    if (i < N1) {
+                        vr_ = (g == gg) ? hr[i] : vr_;
+                        vs_ = (g == gg) ? hs[i] : vs_;
+                    }
+                }
+                hrl[w] = vr_;
+                hsl[w] = vs_;
+            }
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                if (f0 + f < a.nf) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int mb = 0; mb < MBF; ++mb) {
+                        dx4 c = {0, 0, 0, 0};
+#pragma unroll
+                        for (int kb = 0; kb < S::KB; ++kb)
+                            c = MF<double>::mma(A[f][mb][kb], hrl[kb], c);
+#pragma unroll
+                        for (int pp = 0; pp < S::PPB; ++pp) {
+                            const int k = mb * S::PPB + pp;
+                            if (k < N1) {
+                                double sa = 0.0;
+#pragma unroll
+                                for (int w = 0; w < S::EPP; ++w)
+                                    sa = fma(c[pp * S::EPP + w], hsl[w], sa);
+                                v = fma(sa, ht[k], v);
+                            }
+                        }
+                    }
+                    v = slot_sum(v);
+                    if (act && g == 0) a.out[(f0 + f) * a.ostride + p] = v;
+                }
+            }
+        }
+    }
+}
+
 static hipError_t launch_eval_kernel(int n1, int E, const EvArgs &a, const FieldPtrs &F,
                                      const double *B, hipStream_t s)
 {
+#define FP_LAUNCH_MFMA(N1) k_eval_mfma<N1><<<E, kWave, 0, s>>>(a, F, B)
+    switch (n1) {
+        case 2: FP_LAUNCH_MFMA(2); return hipGetLastError();
+        case 3: FP_LAUNCH_MFMA(3); return hipGetLastError();
+        case 4: FP_LAUNCH_MFMA(4); return hipGetLastError();
+        case 5: FP_LAUNCH_MFMA(5); return hipGetLastError();
+        case 6: FP_LAUNCH_MFMA(6); return hipGetLastError();
+        case 7: FP_LAUNCH_MFMA(7); return hipGetLastError();
+        case 8: FP_LAUNCH_MFMA(8); return hipGetLastError();
+        default: break;
+    }
+#undef FP_LAUNCH_MFMA
 #define FP_LAUNCH_GRP(N1) \
     k_eval_grp<N1><<<(E + EvGroup<N1>::G - 1) / EvGroup<N1>::G, kEvThreads, 0, s>>>(a, F, B)
     switch (n1) {
-        case 2: FP_LAUNCH_GRP(2); return hipGetLastError();
-        case 3: FP_LAUNCH_GRP(3); return hipGetLastError();
-        case 4: FP_LAUNCH_GRP(4); return hipGetLastError();
-        case 5: FP_LAUNCH_GRP(5); return hipGetLastError();
-        case 6: FP_LAUNCH_GRP(6); return hipGetLastError();
-        case 7: FP_LAUNCH_GRP(7); return hipGetLastError();
-        case 8: FP_LAUNCH_GRP(8); return hipGetLastError();
         case 9: FP_LAUNCH_GRP(9); return hipGetLastError();
         case 10: FP_LAUNCH_GRP(10); return hipGetLastError();
         default: break;

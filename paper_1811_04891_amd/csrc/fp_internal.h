@@ -57,9 +57,10 @@ struct Work {
     double *res = nullptr;    // M x MC x 4: r, s, t, d2
     double *res_dl = nullptr; // M x MC: delta at the candidate (if delta)
     int *res_in = nullptr;    // M x MC: inside flag
-    int *redo = nullptr;      // M: points without an inside candidate
-    int *redo_n = nullptr;    // 1: their count
-    int *scan_tmp = nullptr;  // block sums of the device scan over E
+    int *redo = nullptr;      // M: second-pass flag per point
+    int *scan_tmp = nullptr;  // block sums of the device scans
+    unsigned *cand_part = nullptr;  // ceil(M / 256): per-block candidate counts
+    unsigned *iter_part = nullptr;  // E: Newton iterations per element
     int *ev_cnt = nullptr;    // E + 1
     int *ev_off = nullptr;    // E + 1
     int *ev_pos = nullptr;    // M

@@ -21,6 +21,7 @@
 
 #include "fp_basis.h"
 #include "fp_internal.h"
+#include "fp_mfma.h"
 
 namespace fp {
 
@@ -29,10 +30,9 @@ struct LocArgs {
     const double *esize;
     const double *bbox;
     const double *obb;   // non-null: also test the oriented box (first pass)
-    const int *idx;      // non-null: task t is point idx[t] (second pass)
-    const int *dcount;   // non-null: number of tasks, read on the device
-    int *redo;           // first pass: points without an inside candidate
-    int *redo_n;
+    int *redo;           // first pass writes 1 for tasks left without an inside
+                         // candidate and with a partial candidate set, else 0
+    const int *only;     // non-null (second pass): tasks with only[t] != 0
     const double *delta;
     const int *esess;
     const int *cell_off;
@@ -52,7 +52,8 @@ struct LocArgs {
     double *res;
     double *res_dl;
     int *res_in;
-    unsigned long long *stats;
+    unsigned *cand_part;  // per k_cand block: the method's candidates (first pass)
+    unsigned *iter_part;  // per element: Newton iterations of its pairs
 };
 
 __device__ __forceinline__ int cell_of(const Grid &g, int a, double x)
@@ -62,9 +63,9 @@ __device__ __forceinline__ int cell_of(const Grid &g, int a, double x)
     return i < 0 ? 0 : (i >= g.nc[a] ? g.nc[a] - 1 : i);
 }
 
-__device__ __forceinline__ int task_count(const LocArgs &a)
+__device__ __forceinline__ bool task_on(const LocArgs &a, int t)
 {
-    return a.dcount ? *a.dcount : a.npts;
+    return t < a.npts && (!a.only || a.only[t] != 0);
 }
 
 // ncand[t] = candidate count | (1 << kFullBit) when the list is the method's
@@ -81,8 +82,10 @@ __global__ __launch_bounds__(256) void k_cand(LocArgs a)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     int naabb = 0;
-    if (t < task_count(a)) {
-        const int p = a.idx ? a.idx[t] : t;
+    if (t < a.npts && a.only && !a.only[t]) {
+        a.ncand[t] = 0;
+    } else if (t < a.npts) {
+        const int p = t;
         const double x0 = a.pts[3 * (long long)p], x1 = a.pts[3 * (long long)p + 1],
                      x2 = a.pts[3 * (long long)p + 2];
         const int ps = a.psess ? a.psess[p] : -1;
@@ -130,19 +133,26 @@ __global__ __launch_bounds__(256) void k_cand(LocArgs a)
         }
         a.ncand[t] = n | (full << kFullBit);
     }
-    if (a.obb) {  // count the method's candidates (first pass covers every point)
-        unsigned long long v = (unsigned long long)naabb;
+    if (a.obb) {  // the method's candidates of this block (first pass covers every point)
+        __shared__ unsigned wsum[256 / kWave];
+        unsigned v = (unsigned)naabb;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-        if ((threadIdx.x & (kWave - 1)) == 0 && v) atomicAdd(&a.stats[3], v);
+        if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned b = 0;
+            for (int i = 0; i < 256 / kWave; ++i) b += wsum[i];
+            a.cand_part[blockIdx.x] = b;
+        }
     }
 }
 
 __global__ __launch_bounds__(256) void k_scatter(LocArgs a)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= task_count(a)) return;
-    const int n = a.ncand[p] & kCountMask;
+    if (p >= a.npts) return;
+    const int n = a.ncand[p] & kCountMask;  // 0 for tasks the pass skips
     for (int k = 0; k < n; ++k) {
         const long long s = (long long)k * a.M + p;
         const int e = a.cand_el[s];
@@ -352,7 +362,10 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
     const BasisPtr<double> B{as_const(basis)};
     const int e = blockIdx.x;
     const int beg = a.elem_off[e], end = a.elem_off[e + 1];
-    if (beg >= end) return;
+    if (beg >= end) {
+        if (threadIdx.x == 0) a.iter_part[e] = 0;
+        return;
+    }
     cptr<double> X = as_const(a.geom + (long long)e * 3 * V);
     const double he = a.esize[e];
     const double rstop = (kResidStop * he) * (kResidStop * he);
@@ -363,7 +376,7 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
         const bool act = q < end;
         const int slot = act ? a.order[q] : 0;
         const int tk = slot % a.M;
-        const int p = a.idx ? a.idx[tk] : tk;
+        const int p = tk;
         double xs[3] = {0.0, 0.0, 0.0};
         if (act) {
             xs[0] = a.pts[3 * (long long)p];
@@ -400,13 +413,44 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
     // wave totals -> counters
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) my_iters += __shfl_xor(my_iters, o, kWave);
-    if (threadIdx.x == 0) {
-        atomicAdd(&a.stats[0], (unsigned long long)(end - beg));
-        atomicAdd(&a.stats[1], my_iters);
-    }
+    if (threadIdx.x == 0) a.iter_part[e] = (unsigned)my_iters;
 }
 
 #include "fp_mfma.inc"
+
+// Fold one pass's partial counts into the handle's counters: one block, so
+// the counters see a handful of atomics per pass.
+__global__ __launch_bounds__(1024) void k_stats(const unsigned *cand_part, int nb,
+                                                const unsigned *iter_part, int E,
+                                                const int *elem_off, long long located,
+                                                unsigned long long *stats)
+{
+    __shared__ unsigned long long sc[1024 / kWave], si[1024 / kWave];
+    unsigned long long c = 0, it = 0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) c += cand_part[i];
+    for (int i = threadIdx.x; i < E; i += blockDim.x) it += iter_part[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        c += __shfl_xor(c, o, kWave);
+        it += __shfl_xor(it, o, kWave);
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        sc[threadIdx.x / kWave] = c;
+        si[threadIdx.x / kWave] = it;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long C = 0, I = 0;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+            C += sc[w];
+            I += si[w];
+        }
+        atomicAdd(&stats[0], (unsigned long long)elem_off[E]);
+        atomicAdd(&stats[1], I);
+        if (located) atomicAdd(&stats[2], (unsigned long long)located);
+        if (C) atomicAdd(&stats[3], C);
+    }
+}
 
 // Owner selection per point (candidates are in ascending element order).
 __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ code,
@@ -414,15 +458,8 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
                                                 double *__restrict__ dist2)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = t < task_count(a);
-    if (a.obb) {  // first pass covers every point once: count them
-        unsigned long long v = live ? 1ULL : 0ULL;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-        if ((threadIdx.x & (kWave - 1)) == 0 && v) atomicAdd(&a.stats[2], v);
-    }
-    if (!live) return;
-    const int p = a.idx ? a.idx[t] : t;
+    if (!task_on(a, t)) return;
+    const int p = t;
     const int nv = a.ncand[t];
     const int n = nv & kCountMask;
     const bool full = (nv >> kFullBit) != 0;
@@ -484,7 +521,7 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
         rst[3 * (long long)p + 2] = o[2];
         dist2[p] = o[3];
     }
-    if (a.obb && c != 0 && !full) a.redo[atomicAdd(a.redo_n, 1)] = p;
+    if (a.obb) a.redo[t] = (c != 0 && !full) ? 1 : 0;
 }
 
 #define FP_DISPATCH_N1(n1, MACRO) \
@@ -579,7 +616,8 @@ int run_findpts(fp_handle *h, const Work &w, int npts, const double *pts, const 
         a.res = w.res;
         a.res_dl = h->delta ? w.res_dl : nullptr;
         a.res_in = w.res_in;
-        a.stats = h->stats;
+        a.cand_part = w.cand_part;
+        a.iter_part = w.iter_part;
 
         hipEvent_t t0 = nullptr, t1 = nullptr, l0 = nullptr, l1 = nullptr;
         if (timed) {
@@ -592,12 +630,11 @@ int run_findpts(fp_handle *h, const Work &w, int npts, const double *pts, const 
         const int pb = (n + 255) / 256;
         int *co = code + start, *eo = el + start;
         double *ro = rst + 3 * (long long)start, *dO = dist2 + start;
-        // first pass: oriented-box candidates; points without an inside
-        // candidate go to the redo list
+        // first pass: oriented-box candidates; tasks without an inside
+        // candidate (and with a partial candidate set) are flagged for the
+        // second pass
         a.obb = h->obb;
         a.redo = w.redo;
-        a.redo_n = w.redo_n;
-        FP_HIP(fill_int(w.redo_n, 0, 1, s));
         FP_HIP(fill_int(w.elem_cnt, 0, (long long)h->E + 1, s));
         k_cand<<<pb, 256, 0, s>>>(a);
         FP_HIP(hipGetLastError());
@@ -609,11 +646,13 @@ int run_findpts(fp_handle *h, const Work &w, int npts, const double *pts, const 
         if (timed) FP_HIP(hipEventRecord(l1, s));
         k_select<<<pb, 256, 0, s>>>(a, co, eo, ro, dO);
         FP_HIP(hipGetLastError());
-        // second pass over the redo list with the axis-aligned candidates
-        // only (sized on the device: kernels past the count return at once)
+        k_stats<<<1, 1024, 0, s>>>(w.cand_part, pb, w.iter_part, h->E, w.elem_off, n, h->stats);
+        FP_HIP(hipGetLastError());
+        // second pass over the flagged tasks with the axis-aligned candidates
+        // only (other tasks get no candidates and keep their result)
         a.obb = nullptr;
-        a.idx = w.redo;
-        a.dcount = w.redo_n;
+        a.redo = nullptr;
+        a.only = w.redo;
         FP_HIP(fill_int(w.elem_cnt, 0, (long long)h->E + 1, s));
         k_cand<<<pb, 256, 0, s>>>(a);
         FP_HIP(hipGetLastError());
@@ -622,6 +661,8 @@ int run_findpts(fp_handle *h, const Work &w, int npts, const double *pts, const 
         FP_HIP(hipGetLastError());
         FP_HIP(launch_locate_kernel(h, a, s));
         k_select<<<pb, 256, 0, s>>>(a, co, eo, ro, dO);
+        FP_HIP(hipGetLastError());
+        k_stats<<<1, 1024, 0, s>>>(w.cand_part, 0, w.iter_part, h->E, w.elem_off, 0, h->stats);
         FP_HIP(hipGetLastError());
         if (timed) {
             FP_HIP(hipEventRecord(t1, s));

@@ -1,0 +1,105 @@
+// Matrix-core building blocks shared by the Newton and interpolation
+// kernels: the 16x16x4 MFMA in binary64 and binary32 with their register
+// layouts, the row blocking of an element's node data, and the sum over the
+// 4 lanes that share a column.
+#pragma once
+
+#include "fp_basis.h"
+
+namespace fp {
+
+typedef double dx4 __attribute__((ext_vector_type(4)));
+typedef float fx4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+struct MF;
+
+template <>
+struct MF<double> {
+    typedef dx4 acc;
+    static __device__ __forceinline__ acc mma(double a, double b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // result row i, column j at lane j + 16 (i % 4), component i / 4
+    static __device__ __forceinline__ int row(int g, int v) { return 4 * v + g; }
+    static __device__ __forceinline__ int grp(int row) { return row % 4; }
+    static __device__ __forceinline__ int comp(int row) { return row / 4; }
+};
+
+template <>
+struct MF<float> {
+    typedef fx4 acc;
+    static __device__ __forceinline__ acc mma(float a, float b, acc c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // result row i, column j at lane j + 16 (i / 4), component i % 4
+    static __device__ __forceinline__ int row(int g, int v) { return 4 * g + v; }
+    static __device__ __forceinline__ int grp(int row) { return row / 4; }
+    static __device__ __forceinline__ int comp(int row) { return row % 4; }
+};
+
+template <int N1>
+struct MShape {
+    static constexpr int JP = N1 <= 4 ? 4 : (N1 <= 8 ? 8 : 16);  // padded rows per plane
+    static constexpr int PPB = 16 / JP;                           // planes per M block
+    static constexpr int NPL = 3 * N1;                            // planes (c, k)
+    static constexpr int MB = (NPL + PPB - 1) / PPB;              // M blocks
+    static constexpr int KB = (N1 + 3) / 4;                       // K blocks (over i)
+    static constexpr int EPP = JP / 4;                            // rows per plane and lane
+    static constexpr int V = N1 * N1 * N1;
+    static constexpr int SB = (V + 15) / 16;                      // node blocks (start scan)
+};
+
+// Sum over the 4 lanes n + 16 g of a slot, by two lane swaps (no LDS):
+// v_permlane16_swap exchanges the odd 16-lane rows of its first operand with
+// the even rows of its second, v_permlane32_swap the upper half of the first
+// with the lower half of the second.  With the same value in both operands
+// the two results are (lower partner, upper partner) in every lane, so the
+// sum is formed in the same order in all 4 lanes: bit-identical totals.
+__device__ __forceinline__ unsigned lo32(double v) { return (unsigned)__double_as_longlong(v); }
+__device__ __forceinline__ unsigned hi32(double v)
+{
+    return (unsigned)((unsigned long long)__double_as_longlong(v) >> 32);
+}
+__device__ __forceinline__ double mk64(unsigned lo, unsigned hi)
+{
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int ROWS>
+__device__ __forceinline__ double swap_add(double v)
+{
+    const unsigned l = lo32(v), h = hi32(v);
+    if constexpr (ROWS == 16) {
+        const auto a = __builtin_amdgcn_permlane16_swap(l, l, false, false);
+        const auto b = __builtin_amdgcn_permlane16_swap(h, h, false, false);
+        return mk64(a[0], b[0]) + mk64(a[1], b[1]);
+    } else {
+        const auto a = __builtin_amdgcn_permlane32_swap(l, l, false, false);
+        const auto b = __builtin_amdgcn_permlane32_swap(h, h, false, false);
+        return mk64(a[0], b[0]) + mk64(a[1], b[1]);
+    }
+}
+
+template <int ROWS>
+__device__ __forceinline__ float swap_add(float v)
+{
+    const unsigned l = __float_as_uint(v);
+    if constexpr (ROWS == 16) {
+        const auto a = __builtin_amdgcn_permlane16_swap(l, l, false, false);
+        return __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    } else {
+        const auto a = __builtin_amdgcn_permlane32_swap(l, l, false, false);
+        return __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    }
+}
+
+template <class T>
+__device__ __forceinline__ T slot_sum(T v)
+{
+    return swap_add<32>(swap_add<16>(v));
+}
+
+}  // namespace fp
