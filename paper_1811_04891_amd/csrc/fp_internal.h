@@ -97,6 +97,7 @@ struct fp_handle {
     int max_cell = 0;
     int *cell_off = nullptr;   // ncell + 1
     int *cell_el = nullptr;    // nnz
+    float4 *cell_box = nullptr; // 2 nnz: binary32 outward box + element id per entry
 
     // workspace of the handle's own calls (max_points per pass)
     int MC = 1;                 // longest hash-cell list (>= 1)

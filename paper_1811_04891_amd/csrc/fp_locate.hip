@@ -36,7 +36,7 @@ struct LocArgs {
     const double *delta;
     const int *esess;
     const int *cell_off;
-    const int *cell_el;
+    const float4 *cell_box;  // per cell entry: binary32 outward box, element id
     Grid g;
     const double *pts;
     const int *psess;
@@ -68,6 +68,10 @@ __device__ __forceinline__ bool task_on(const LocArgs &a, int t)
     return t < a.npts && (!a.only || a.only[t] != 0);
 }
 
+// res_in of a pair: 0 = solved, not inside; 1 = inside; kUnsolved = left by the
+// mixed-precision first pass to the binary64 second pass
+constexpr int kUnsolved = 2;
+
 // ncand[t] = candidate count | (1 << kFullBit) when the list is the method's
 // whole candidate set (no second pass needed for that point)
 constexpr int kFullBit = 30;
@@ -98,6 +102,9 @@ __global__ __launch_bounds__(256) void k_cand(LocArgs a)
                                 (long long)g.nc[0] * (cell_of(g, 1, x1) +
                                                       (long long)g.nc[1] * cell_of(g, 2, x2));
             const int qb = a.cell_off[c], qe = a.cell_off[c + 1];
+            // rounding is monotonic: x in [lo, hi] implies (float)x in the
+            // outward-rounded binary32 box
+            const float xf0 = (float)x0, xf1 = (float)x1, xf2 = (float)x2;
             int *ce = a.cand_el + t;
             int *cp = a.cand_pos + t;
             // pass 0: oriented-box filter (first pass only); pass 1: every
@@ -105,7 +112,13 @@ __global__ __launch_bounds__(256) void k_cand(LocArgs a)
             // has its full candidate set and needs no second pass)
             for (int pass = a.obb ? 0 : 1; pass < 2 && n == 0; ++pass) {
                 for (int q = qb; q < qe; ++q) {
-                    const int e = a.cell_el[q];
+                    // binary32 box (outward-rounded: a superset), then the
+                    // exact binary64 box of the method
+                    const float4 lo = a.cell_box[2 * (long long)q], hi = a.cell_box[2 * (long long)q + 1];
+                    if (xf0 < lo.x || xf0 > hi.x || xf1 < lo.y || xf1 > hi.y || xf2 < lo.z ||
+                        xf2 > hi.z)
+                        continue;
+                    const int e = __float_as_int(lo.w);
                     const double *b = a.bbox + 6 * (long long)e;
                     if (x0 < b[0] || x0 > b[1] || x1 < b[2] || x1 > b[3] || x2 < b[4] || x2 > b[5])
                         continue;
@@ -465,8 +478,12 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
     const bool full = (nv >> kFullBit) != 0;
     auto S =[&](int k) { return (long long)k * a.M + t; };
     int w = -1, c = 2;
-    bool anyin = false;
-    for (int k = 0; k < n; ++k) anyin |= a.res_in[S(k)] != 0;
+    bool anyin = false, unsolved = false;
+    for (int k = 0; k < n; ++k) {
+        const int in = a.res_in[S(k)];
+        anyin |= in == 1;
+        unsolved |= in == kUnsolved;
+    }
     if (anyin) {
         c = 0;
         if (a.res_dl) {
@@ -476,11 +493,11 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
             double bd = -INFINITY;
             bool hv = false;
             for (int k = 0; k < n; ++k) {
-                if (!a.res_in[S(k)]) continue;
+                if (a.res_in[S(k)] != 1) continue;
                 const int sk = a.esess ? a.esess[a.cand_el[S(k)]] : 0;
                 double sd = -INFINITY;
                 for (int u = 0; u < n; ++u) {
-                    if (!a.res_in[S(u)]) continue;
+                    if (a.res_in[S(u)] != 1) continue;
                     const int su = a.esess ? a.esess[a.cand_el[S(u)]] : 0;
                     if (su == sk) sd = fmax(sd, a.res_dl[S(u)]);
                 }
@@ -491,14 +508,16 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
                 }
             }
             for (int k = 0; k < n && w < 0; ++k) {
-                if (!a.res_in[S(k)]) continue;
+                if (a.res_in[S(k)] != 1) continue;
                 const int sk = a.esess ? a.esess[a.cand_el[S(k)]] : 0;
                 if (sk == bs) w = k;
             }
         } else {
             for (int k = 0; k < n && w < 0; ++k)
-                if (a.res_in[S(k)]) w = k;
+                if (a.res_in[S(k)] == 1) w = k;
         }
+    } else if (unsolved) {
+        c = 1;  // provisional: the second pass decides
     } else if (n > 0) {
         c = 1;
         w = 0;
@@ -521,7 +540,7 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
         rst[3 * (long long)p + 2] = o[2];
         dist2[p] = o[3];
     }
-    if (a.obb) a.redo[t] = (c != 0 && !full) ? 1 : 0;
+    if (a.obb) a.redo[t] = (c != 0 && (!full || unsolved)) ? 1 : 0;
 }
 
 #define FP_DISPATCH_N1(n1, MACRO) \
@@ -547,12 +566,13 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
 static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, hipStream_t s)
 {
 #define FP_LAUNCH_LOCATE(N1) k_locate<N1><<<h->E, kWave, 0, s>>>(a, h->d_basis)
-#define FP_LAUNCH_MFMA(N1)                                                                \
-    do {                                                                                  \
-        if (h->precision == FP_PREC_MIXED)                                                \
-            k_locate_mfma<N1, true><<<h->E, kWave, 0, s>>>(a, h->d_basis, h->d_basis32);  \
-        else                                                                              \
-            k_locate_mfma<N1, false><<<h->E, kWave, 0, s>>>(a, h->d_basis, h->d_basis32); \
+// mixed precision: first pass only (the second pass is binary64)
+#define FP_LAUNCH_MFMA(N1)                                                          \
+    do {                                                                            \
+        if (h->precision == FP_PREC_MIXED && a.obb)                                 \
+            k_locate_mixed<N1><<<h->E, kWave, 0, s>>>(a, h->d_basis, h->d_basis32); \
+        else                                                                        \
+            k_locate_mfma<N1><<<h->E, kWave, 0, s>>>(a, h->d_basis);                \
     } while (0)
     switch (h->n1) {
         case 2: FP_LAUNCH_MFMA(2); break;
@@ -600,7 +620,7 @@ int run_findpts(fp_handle *h, const Work &w, int npts, const double *pts, const 
         a.delta = h->delta;
         a.esess = h->esess;
         a.cell_off = h->cell_off;
-        a.cell_el = h->cell_el;
+        a.cell_box = h->cell_box;
         a.g = h->grid;
         a.pts = pts + 3 * (long long)start;
         a.psess = pt_session ? pt_session + start : nullptr;

@@ -412,6 +412,31 @@ __global__ __launch_bounds__(256) void k_hash_sort(const int *__restrict__ off,
     atomicMax(maxlen, n);
 }
 
+// Per cell-list entry, the element's box in binary32 rounded outward (never
+// smaller than the binary64 box) with the element id in the spare slot: the
+// candidate lookup streams a cell's entries contiguously and tests the exact
+// binary64 box only for the survivors.
+__global__ __launch_bounds__(256) void k_cellbox(const double *__restrict__ bbox,
+                                                 const int *__restrict__ cell_el, long long nnz,
+                                                 float4 *__restrict__ cell_box)
+{
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nnz) return;
+    const int e = cell_el[q];
+    const double *b = bbox + 6 * (long long)e;
+    float lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float l = (float)b[2 * a], u = (float)b[2 * a + 1];
+        if ((double)l > b[2 * a]) l = nextafterf(l, -INFINITY);
+        if ((double)u < b[2 * a + 1]) u = nextafterf(u, INFINITY);
+        lo[a] = l;
+        hi[a] = u;
+    }
+    cell_box[2 * q] = make_float4(lo[0], lo[1], lo[2], __int_as_float(e));
+    cell_box[2 * q + 1] = make_float4(hi[0], hi[1], hi[2], 0.0f);
+}
+
 }  // namespace fp
 
 // ---------------------------------------------------------------------------
@@ -483,7 +508,8 @@ using namespace fp;
 static void release(fp_handle *h)
 {
     void *ptrs[] = {h->d_basis, h->d_basis32, h->geom, h->geom32, h->esize, h->bbox, h->obb,
-                    h->esess, h->delta, h->cell_off, h->cell_el, h->work_mem, h->scan_tmp,
+                    h->esess, h->delta, h->cell_off, h->cell_el, h->cell_box, h->work_mem,
+                    h->scan_tmp,
                     h->stats};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -668,6 +694,11 @@ extern "C" int findpts_setup(fp_handle **out, const double *x, const double *y,
     (void)hipFree(cnt);
     (void)hipFree(d_flag);
     h->max_cell = maxlen;
+    FP_HIP_H(dalloc(h, &h->cell_box, 2 * (size_t)nnz));
+    if (nnz > 0) {
+        k_cellbox<<<(int)((nnz + 255) / 256), 256, 0, s>>>(h->bbox, h->cell_el, nnz, h->cell_box);
+        FP_HIP_H(hipGetLastError());
+    }
     h->MC = std::max(1, maxlen);
 
     // workspace
