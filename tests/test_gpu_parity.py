@@ -295,3 +295,71 @@ def test_two_sessions_overlap_subset(dev):
     found = g[0] != 2
     assert np.all(sess[g[1][found]] != tags.numpy()[found])
     _say(f"two sessions ok {st}")
+
+
+def _sampled(om, pts, g, idx, hs, psess=None, every=4):
+    o = om.findpts(pts[idx], None if psess is None else psess[idx])
+    return compare_locate(om, pts[idx], tuple(a[idx] for a in g), o, hs, TOL,
+                          check_residual_every=every)
+
+
+def _invariants(g, E):
+    gc, ge, gr, gd = g
+    assert np.all((gc >= 0) & (gc <= 2))
+    assert np.all((ge >= -1) & (ge < E))
+    assert np.all(np.abs(gr) <= 1.0)
+    assert np.all((gc == 2) == np.isinf(gd))
+    assert np.all((gc == 2) == (ge == -1))
+
+
+def test_c5_large_box_full_size_sampled(dev):
+    """200,000 curved elements of order 7, 2e7 points clustered near spheres,
+    in passes of 2^20 points (the benchmark's launch configuration); a seeded
+    sample of 20,000 outputs against the oracle, whole-output invariants, and
+    the mixed-precision path against binary64 on every point."""
+    fp = _fp()
+    _say("case: large box C5, 200,000 elements, 2e7 points, sampled parity")
+    mesh = w.big_box_c5()
+    pts = w.queries_c5()
+    h, g, _ = _run(fp, mesh, pts, dev, max_points=1 << 20)
+    _invariants(g, mesh.E)
+    rng = np.random.default_rng(55)
+    idx = np.sort(rng.choice(len(pts), 20_000, replace=False))
+    om = oracle.OracleMesh.from_mesh(mesh, TOL)
+    _, hs = om.bbox()
+    st = _sampled(om, pts.numpy(), g, idx, hs)
+    assert st["inside"] > 0.8 * len(idx) and st["border"] + st["notfound"] > 0
+    _say(f"c5 fp64 ok {st}")
+    fp.findpts_set_precision(h, fp.FP_PREC_MIXED)
+    code, el, rst, d2 = fp.findpts(h, pts.to(dev))
+    torch.cuda.synchronize()
+    gm = (code.cpu().numpy(), el.cpu().numpy(), rst.cpu().numpy(), d2.cpu().numpy())
+    _invariants(gm, mesh.E)
+    assert np.array_equal(gm[0], g[0])
+    ties = gm[1] != g[1]
+    assert np.all(np.min(1 - np.abs(gm[2][ties]), axis=1) <= 1e-10)
+    st = _sampled(om, pts.numpy(), gm, idx, hs)
+    _say(f"c5 mixed ok {st}, {int(ties.sum())} face ties vs fp64")
+    h.free()
+
+
+def test_c3_interface_faces_full_size_sampled(dev):
+    """Two overlapping sessions, 1.2e6 points on the interface faces tagged
+    with their session, one pass of 2^21 points; sampled parity (distance
+    discriminator and session exclusion included) and invariants."""
+    fp = _fp()
+    _say("case: two sessions C3, 1.2e6 interface-face points, sampled parity")
+    mesh = w.overlap_c3()
+    pts, tags = w.queries_c3(n=1_200_000)
+    h, g, _ = _run(fp, mesh, pts, dev, max_points=1 << 21, psess=tags)
+    _invariants(g, mesh.E)
+    sess = mesh.session.numpy()
+    found = g[0] != 2
+    assert np.all(sess[g[1][found]] != tags.numpy()[found])
+    rng = np.random.default_rng(33)
+    idx = np.sort(rng.choice(len(pts), 20_000, replace=False))
+    om = oracle.OracleMesh.from_mesh(mesh, TOL)
+    _, hs = om.bbox()
+    st = _sampled(om, pts.numpy(), g, idx, hs, psess=tags.numpy())
+    _say(f"c3 full ok {st}")
+    h.free()

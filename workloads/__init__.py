@@ -26,6 +26,7 @@ from .meshes import (  # noqa: F401
     queries_c1,
     queries_c2,
     queries_c3,
+    queries_c5,
     c3_interface_nodes,
     poly_fields,
     ref_poly_fields,

@@ -327,6 +327,24 @@ def queries_c3(kind="faces", n=1_200_000, seed=3, device="cpu"):
             torch.as_tensor(tags[perm], dtype=torch.int32, device=device))
 
 
+def queries_c5(n=20_000_000, seed=5, device="cpu") -> torch.Tensor:
+    """Points clustered near 8 random interior spheres of the large box.
+
+    Centres uniform in [0.2, 1.8] x [0.2, 0.8] x [0.2, 0.6] (the domain shrunk
+    by 0.2), radii U(0.1, 0.3); each point is uniform on its sphere, moved
+    along the normal by N(0, (0.5 h)^2) with h = 0.02 (points outside the
+    domain are kept).  Shape (n, 3).
+    """
+    rng = np.random.default_rng(seed)
+    cen = rng.uniform((0.2, 0.2, 0.2), (1.8, 0.8, 0.6), (8, 3))
+    rad = rng.uniform(0.1, 0.3, 8)
+    which = rng.integers(0, 8, n)
+    d = rng.standard_normal((n, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    r = rad[which] + rng.normal(0.0, 0.5 * 0.02, n)
+    return _t(cen[which] + r[:, None] * d, device)
+
+
 def c3_interface_nodes(mesh: Mesh):
     """All GLL nodes of the two-session interface faces, tagged by session.
 
