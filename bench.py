@@ -342,6 +342,31 @@ def main():
                        "method_candidates_per_point": cands / max(located, 1),
                        "codes": codes.tolist()},
     }
+    # moving mesh: re-setup on the device after each rigid rotation (0.01 rad)
+    # of the annulus, then findpts + findpts_eval on the moved mesh
+    import math
+    upd = []
+    for k in range(1, 6):
+        c, sn = math.cos(0.01 * k), math.sin(0.01 * k)
+        xk = (c * mesh.x - sn * mesh.y).contiguous()
+        yk = (sn * mesh.x + c * mesh.y).contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fp.findpts_update(h, xk, yk, mesh.z)
+        torch.cuda.synchronize()
+        upd.append(time.perf_counter() - t0)
+    fp.findpts_set_precision(h, head)
+    ev2a, ev2b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev2a.record(stream)
+    step()
+    ev2b.record(stream)
+    torch.cuda.synchronize()
+    moved_codes = np.bincount(code.cpu().numpy(), minlength=3).tolist()
+    rec["moving_mesh"] = {
+        "update_ms": 1e3 * float(np.median(upd)), "updates": len(upd),
+        "setup_ms": 1e3 * setup_s, "step_ms_after_update": ev2a.elapsed_time(ev2b),
+        "codes_after_update": moved_codes,
+    }
     oname = "mixed" if other == fp.FP_PREC_MIXED else "fp64"
     rec[oname] = {
         "value": P / (ms_o / 1e3), "ms_per_step": ms_o,

@@ -86,7 +86,7 @@ enum fp_precision {
  *                findpts / findpts_eval calls are processed in passes.  The
  *                workspace is sized from it at setup.
  *   precision    an fp_precision value.
- * Synchronises `stream` (twice: to size the hash grid and its workspace).
+ * Synchronises `stream` (to size the hash grid and its workspace).
  * Errors: FP_EINVAL (NULL pointers, E < 1, bad tol/precision/max_points,
  * non-finite coordinates, detected on the device), FP_ERANGE (N), FP_ENOMEM,
  * FP_EHIP.  Inverted or degenerate elements are accepted (never rejected).
@@ -95,6 +95,26 @@ FP_API int findpts_setup(fp_handle **h, const double *x, const double *y,
                   const double *z, int E, int N, double tol,
                   const int *elem_session, const double *delta,
                   int max_points, int precision, void *stream);
+
+/*
+ * findpts_update -- post new node coordinates of the same mesh (same E, N,
+ * sessions, tolerance) to a set-up handle, for moving or deforming meshes,
+ * whose donor elements must be found again after every timestep (Section 1,
+ * the overlapping-grid challenges).  Recomputes, on the device, the packed
+ * copies, element boxes and sizes, oriented boxes and the hash grid.
+ *   x, y, z  node coordinates, layout as in findpts_setup (copied).
+ *   delta    new distance field (E*(N+1)^3) or NULL to keep the current one;
+ *            FP_ESTATE if the handle was set up without one.
+ * Allocates only when the new hash grid needs more room than any earlier
+ * one.  Synchronises `stream` three times.  Calls on the handle that are
+ * still in flight must have finished (the serving layer must not be running
+ * requests on it).  Errors: FP_EINVAL (NULL, non-finite coordinates: the
+ * handle must then be updated again before use), FP_ESTATE, FP_ERANGE,
+ * FP_EHIP.  Results afterwards equal those of a handle set up on the new
+ * coordinates.
+ */
+FP_API int findpts_update(fp_handle *h, const double *x, const double *y, const double *z,
+                          const double *delta, void *stream);
 
 /*
  * findpts -- locate npts points (Section 2.1: hash lookup, elementwise

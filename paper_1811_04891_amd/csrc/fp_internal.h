@@ -96,6 +96,9 @@ struct fp_handle {
     long long ncell = 0, nnz = 0;
     int max_cell = 0;
     int *cell_off = nullptr;   // ncell + 1
+    int *cell_cnt = nullptr;   // ncell + 1 (hash build)
+    long long cell_cap = 0;    // allocated length of cell_off / cell_cnt
+    long long nnz_cap = 0;     // allocated entries of cell_el / cell_box
     int *cell_el = nullptr;    // nnz
     float4 *cell_box = nullptr; // 2 nnz: binary32 outward box + element id per entry
 
@@ -103,6 +106,10 @@ struct fp_handle {
     int MC = 1;                 // longest hash-cell list (>= 1)
     fp::Work work{};
     void *work_mem = nullptr;
+    size_t work_bytes = 0;
+    int *d_flag = nullptr;      // setup scratch: flags, longest cell list
+    double *d_g = nullptr;      // setup scratch: global box
+    double *d_binv = nullptr;   // Bernstein-to-nodal inverse (n1 x n1)
     int *scan_tmp = nullptr;    // setup's scans (cells)
     int scan_tmp_n = 0;
 

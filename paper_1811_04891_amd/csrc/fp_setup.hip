@@ -508,9 +508,8 @@ using namespace fp;
 static void release(fp_handle *h)
 {
     void *ptrs[] = {h->d_basis, h->d_basis32, h->geom, h->geom32, h->esize, h->bbox, h->obb,
-                    h->esess, h->delta, h->cell_off, h->cell_el, h->cell_box, h->work_mem,
-                    h->scan_tmp,
-                    h->stats};
+                    h->esess, h->delta, h->cell_off, h->cell_cnt, h->cell_el, h->cell_box,
+                    h->work_mem, h->scan_tmp, h->stats, h->d_flag, h->d_g, h->d_binv};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &t : h->timed) {
@@ -539,6 +538,134 @@ static hipError_t dalloc(fp_handle *h, T **p, size_t count)
             return rc_;                             \
         }                                           \
     } while (0)
+
+// Geometry products of the current node coordinates: packed copies, element
+// boxes and sizes, oriented boxes, hash grid (with the per-entry binary32
+// boxes) and the longest cell list.  Device arrays keep their allocation when
+// large enough (an update of a moving mesh allocates only when its hash needs
+// more room than before).  Synchronises `s` three times (global box, entry
+// count, longest list).
+static int build_geometry(fp_handle *h, const double *x, const double *y, const double *z,
+                          hipStream_t s, const char *who)
+{
+    const int E = h->E;
+    const long long V = h->V, EV = (long long)E * V;
+    const int n1 = h->n1;
+    FP_HIP(hipMemsetAsync(h->d_flag, 0, sizeof(int), s));
+    {
+        long long blocks = std::min<long long>((EV + 255) / 256, 256LL * 64);
+        k_pack<<<(int)blocks, 256, 0, s>>>(x, y, z, EV, (int)V, h->geom, h->geom32, h->d_flag);
+        FP_HIP(hipGetLastError());
+    }
+    k_bbox<<<E, kWave, 2 * V * sizeof(double), s>>>(h->geom, n1, h->d_binv, h->bbox, h->esize);
+    FP_HIP(hipGetLastError());
+    k_obb<<<E, kWave, 2 * V * sizeof(double), s>>>(h->geom, n1, h->d_binv, h->bbox, h->esize,
+                                                    h->obb);
+    FP_HIP(hipGetLastError());
+    k_gbox<<<1, 256, 0, s>>>(h->bbox, E, h->d_g);
+    FP_HIP(hipGetLastError());
+    double gb[6];
+    int bad = 0;
+    FP_HIP(hipMemcpyAsync(gb, h->d_g, sizeof gb, hipMemcpyDeviceToHost, s));
+    FP_HIP(hipMemcpyAsync(&bad, h->d_flag, sizeof bad, hipMemcpyDeviceToHost, s));
+    FP_HIP(hipStreamSynchronize(s));
+    if (bad) {
+        set_error(std::string(who) + ": non-finite node coordinates");
+        return FP_EINVAL;
+    }
+
+    // hash grid: about 8 E cells (two per element and axis, so each cell
+    // lists few elements), cell aspect following the extents
+    Grid g{};
+    double ext[3], vol = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        g.lo[a] = gb[2 * a];
+        g.hi[a] = gb[2 * a + 1];
+        ext[a] = g.hi[a] - g.lo[a];
+        if (!(ext[a] > 0.0)) ext[a] = 1e-300;
+        vol *= ext[a];
+    }
+    const double dens = std::cbrt(8.0 * (double)E / vol);
+    for (int a = 0; a < 3; ++a) {
+        double n = std::floor(ext[a] * dens + 0.5);
+        n = std::min(std::max(n, 1.0), 1024.0);
+        g.nc[a] = (int)n;
+        g.inv[a] = g.nc[a] / ext[a];
+    }
+    h->grid = g;
+    h->ncell = (long long)g.nc[0] * g.nc[1] * g.nc[2];
+    if (h->ncell + 1 > h->cell_cap) {
+        (void)hipFree(h->cell_off);
+        (void)hipFree(h->cell_cnt);
+        (void)hipFree(h->scan_tmp);
+        h->bytes -= sizeof(int) * (2 * (size_t)h->cell_cap + (size_t)h->scan_tmp_n);
+        h->cell_off = h->cell_cnt = h->scan_tmp = nullptr;
+        h->cell_cap = h->ncell + 1;
+        FP_HIP(dalloc(h, &h->cell_off, h->cell_cap));
+        FP_HIP(dalloc(h, &h->cell_cnt, h->cell_cap));
+        h->scan_tmp_n = std::max(scan_tmp_size(h->ncell), scan_tmp_size((long long)E + 1));
+        FP_HIP(dalloc(h, &h->scan_tmp, h->scan_tmp_n));
+    }
+    int *cnt = h->cell_cnt;
+    FP_HIP(fill_int(cnt, 0, h->ncell + 1, s));
+    const int eb = (E + 255) / 256;
+    k_hash_pass<<<eb, 256, 0, s>>>(h->bbox, E, g, 0, cnt, nullptr, nullptr);
+    FP_HIP(hipGetLastError());
+    FP_HIP(scan_exclusive(cnt, h->cell_off, (int)h->ncell, h->scan_tmp, s));
+    int nnz = 0;
+    FP_HIP(hipMemcpyAsync(&nnz, h->cell_off + h->ncell, sizeof(int), hipMemcpyDeviceToHost, s));
+    FP_HIP(hipStreamSynchronize(s));
+    h->nnz = nnz;
+    if (nnz > h->nnz_cap || !h->cell_el) {
+        (void)hipFree(h->cell_el);
+        (void)hipFree(h->cell_box);
+        h->bytes -= (sizeof(int) + 2 * sizeof(float4)) * (size_t)h->nnz_cap;
+        h->cell_el = nullptr;
+        h->cell_box = nullptr;
+        h->nnz_cap = nnz;
+        FP_HIP(dalloc(h, &h->cell_el, (size_t)nnz));
+        FP_HIP(dalloc(h, &h->cell_box, 2 * (size_t)nnz));
+    }
+    FP_HIP(fill_int(cnt, 0, h->ncell, s));
+    k_hash_pass<<<eb, 256, 0, s>>>(h->bbox, E, g, 1, cnt, h->cell_off, h->cell_el);
+    FP_HIP(hipGetLastError());
+    FP_HIP(hipMemsetAsync(h->d_flag, 0, sizeof(int), s));
+    k_hash_sort<<<(int)((h->ncell + 255) / 256), 256, 0, s>>>(h->cell_off, h->cell_el, h->ncell,
+                                                              h->d_flag);
+    FP_HIP(hipGetLastError());
+    int maxlen = 0;
+    FP_HIP(hipMemcpyAsync(&maxlen, h->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    FP_HIP(hipStreamSynchronize(s));
+    h->max_cell = maxlen;
+    if (nnz > 0) {
+        k_cellbox<<<(int)((nnz + 255) / 256), 256, 0, s>>>(h->bbox, h->cell_el, nnz, h->cell_box);
+        FP_HIP(hipGetLastError());
+    }
+    h->MC = std::max(1, maxlen);
+    return FP_OK;
+}
+
+// The handle's own workspace, (re)carved when the longest cell list grew.
+static int ensure_workspace(fp_handle *h, const char *who)
+{
+    if (h->work_mem && h->MC <= h->work.MC) return FP_OK;
+    if ((double)h->max_points * (double)h->MC >= 2147483647.0) {
+        set_error(std::string(who) +
+                  ": max_points x longest cell list exceeds 2^31; lower max_points");
+        return FP_ERANGE;
+    }
+    if (h->work_mem) {
+        FP_HIP(hipDeviceSynchronize());  // calls in flight may still use it
+        (void)hipFree(h->work_mem);
+        h->bytes -= h->work_bytes;
+        h->work_mem = nullptr;
+    }
+    h->work_bytes = work_bytes(h->E, h->MC, h->max_points, h->delta != nullptr);
+    FP_HIP(hipMalloc(&h->work_mem, h->work_bytes));
+    h->bytes += h->work_bytes;
+    work_carve(h->work, (char *)h->work_mem, h->E, h->MC, h->max_points, h->delta != nullptr);
+    return FP_OK;
+}
 
 extern "C" int findpts_setup(fp_handle **out, const double *x, const double *y,
                              const double *z, int E, int N, double tol,
@@ -585,10 +712,7 @@ extern "C" int findpts_setup(fp_handle **out, const double *x, const double *y,
     }
     const long long EV = (long long)E * V;
 
-    // mesh copy
-    int *d_flag = nullptr;
-    double *d_g = nullptr;
-    double *d_binv = nullptr;
+    // mesh-size arrays (kept for the handle's lifetime)
     FP_HIP_H(dalloc(h, &h->geom, 3 * EV));
     FP_HIP_H(dalloc(h, &h->geom32, 3 * EV));  // kept for either precision
     FP_HIP_H(dalloc(h, &h->esize, E));
@@ -597,9 +721,18 @@ extern "C" int findpts_setup(fp_handle **out, const double *x, const double *y,
     FP_HIP_H(dalloc(h, &h->stats, 4));
     FP_HIP_H(dalloc(h, &h->d_basis, 2 * kMaxN1));
     FP_HIP_H(dalloc(h, &h->d_basis32, 2 * kMaxN1));
+    FP_HIP_H(dalloc(h, &h->d_flag, 1));
+    FP_HIP_H(dalloc(h, &h->d_g, 6));
+    FP_HIP_H(dalloc(h, &h->d_binv, (size_t)(n1 * n1)));
     FP_HIP_H(hipMemcpyAsync(h->d_basis, &h->basis, sizeof(Basis), hipMemcpyHostToDevice, s));
     FP_HIP_H(hipMemcpyAsync(h->d_basis32, &h->basis32, sizeof(Basis32), hipMemcpyHostToDevice, s));
     FP_HIP_H(hipMemsetAsync(h->stats, 0, 4 * sizeof(unsigned long long), s));
+    {
+        const std::vector<double> binv = bernstein_to_nodal_inverse(N, h->basis.z);
+        FP_HIP_H(hipMemcpyAsync(h->d_binv, binv.data(), sizeof(double) * n1 * n1,
+                                hipMemcpyHostToDevice, s));
+        FP_HIP_H(hipStreamSynchronize(s));  // the host vector goes out of scope
+    }
     if (elem_session) {
         FP_HIP_H(dalloc(h, &h->esess, E));
         FP_HIP_H(hipMemcpyAsync(h->esess, elem_session, sizeof(int) * E,
@@ -610,112 +743,38 @@ extern "C" int findpts_setup(fp_handle **out, const double *x, const double *y,
         FP_HIP_H(hipMemcpyAsync(h->delta, delta, sizeof(double) * EV,
                                 hipMemcpyDeviceToDevice, s));
     }
-    FP_HIP_H(hipMalloc((void **)&d_flag, sizeof(int)));
-    FP_HIP_H(hipMalloc((void **)&d_g, 6 * sizeof(double)));
-    FP_HIP_H(hipMalloc((void **)&d_binv, sizeof(double) * n1 * n1));
-    FP_HIP_H(hipMemsetAsync(d_flag, 0, sizeof(int), s));
-    {
-        long long blocks = std::min<long long>((EV + 255) / 256, 256LL * 64);
-        k_pack<<<(int)blocks, 256, 0, s>>>(x, y, z, EV, (int)V, h->geom, h->geom32, d_flag);
-        FP_HIP_H(hipGetLastError());
-    }
-    std::vector<double> binv = bernstein_to_nodal_inverse(N, h->basis.z);
-    FP_HIP_H(hipMemcpyAsync(d_binv, binv.data(), sizeof(double) * n1 * n1,
-                            hipMemcpyHostToDevice, s));
-    k_bbox<<<E, kWave, 2 * V * sizeof(double), s>>>(h->geom, (int)n1, d_binv, h->bbox,
-                                                     h->esize);
-    FP_HIP_H(hipGetLastError());
-    k_obb<<<E, kWave, 2 * V * sizeof(double), s>>>(h->geom, (int)n1, d_binv, h->bbox,
-                                                    h->esize, h->obb);
-    FP_HIP_H(hipGetLastError());
-    k_gbox<<<1, 256, 0, s>>>(h->bbox, E, d_g);
-    FP_HIP_H(hipGetLastError());
-    double gb[6];
-    int bad = 0;
-    FP_HIP_H(hipMemcpyAsync(gb, d_g, sizeof gb, hipMemcpyDeviceToHost, s));
-    FP_HIP_H(hipMemcpyAsync(&bad, d_flag, sizeof bad, hipMemcpyDeviceToHost, s));
-    FP_HIP_H(hipStreamSynchronize(s));
-    (void)hipFree(d_binv);
-    (void)hipFree(d_g);
-    if (bad) {
-        (void)hipFree(d_flag);
+    int rc = build_geometry(h, x, y, z, s, "findpts_setup");
+    if (rc == FP_OK) rc = ensure_workspace(h, "findpts_setup");
+    if (rc != FP_OK) {
         release(h);
-        set_error("findpts_setup: non-finite node coordinates");
-        return FP_EINVAL;
-    }
-
-    // hash grid: about 8 E cells (two per element and axis, so each cell
-    // lists few elements), cell aspect following the extents
-    Grid g{};
-    double ext[3], vol = 1.0;
-    for (int a = 0; a < 3; ++a) {
-        g.lo[a] = gb[2 * a];
-        g.hi[a] = gb[2 * a + 1];
-        ext[a] = g.hi[a] - g.lo[a];
-        if (!(ext[a] > 0.0)) ext[a] = 1e-300;
-        vol *= ext[a];
-    }
-    const double dens = std::cbrt(8.0 * (double)E / vol);
-    for (int a = 0; a < 3; ++a) {
-        double n = std::floor(ext[a] * dens + 0.5);
-        n = std::min(std::max(n, 1.0), 1024.0);
-        g.nc[a] = (int)n;
-        g.inv[a] = g.nc[a] / ext[a];
-    }
-    h->grid = g;
-    h->ncell = (long long)g.nc[0] * g.nc[1] * g.nc[2];
-    int *cnt = nullptr;
-    FP_HIP_H(dalloc(h, &h->cell_off, h->ncell + 1));
-    FP_HIP_H(hipMalloc((void **)&cnt, sizeof(int) * (h->ncell + 1)));
-    int tmpn = std::max(scan_tmp_size(h->ncell), scan_tmp_size((long long)E + 1));
-    h->scan_tmp_n = tmpn;
-    FP_HIP_H(dalloc(h, &h->scan_tmp, tmpn));
-    FP_HIP_H(fill_int(cnt, 0, h->ncell + 1, s));
-    const int eb = (E + 255) / 256;
-    k_hash_pass<<<eb, 256, 0, s>>>(h->bbox, E, g, 0, cnt, nullptr, nullptr);
-    FP_HIP_H(hipGetLastError());
-    FP_HIP_H(scan_exclusive(cnt, h->cell_off, (int)h->ncell, h->scan_tmp, s));
-    int nnz = 0;
-    FP_HIP_H(hipMemcpyAsync(&nnz, h->cell_off + h->ncell, sizeof(int),
-                            hipMemcpyDeviceToHost, s));
-    FP_HIP_H(hipStreamSynchronize(s));
-    h->nnz = nnz;
-    FP_HIP_H(dalloc(h, &h->cell_el, nnz));
-    FP_HIP_H(fill_int(cnt, 0, h->ncell, s));
-    k_hash_pass<<<eb, 256, 0, s>>>(h->bbox, E, g, 1, cnt, h->cell_off, h->cell_el);
-    FP_HIP_H(hipGetLastError());
-    FP_HIP_H(hipMemsetAsync(d_flag, 0, sizeof(int), s));
-    k_hash_sort<<<(int)((h->ncell + 255) / 256), 256, 0, s>>>(h->cell_off, h->cell_el,
-                                                              h->ncell, d_flag);
-    FP_HIP_H(hipGetLastError());
-    int maxlen = 0;
-    FP_HIP_H(hipMemcpyAsync(&maxlen, d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    FP_HIP_H(hipStreamSynchronize(s));
-    (void)hipFree(cnt);
-    (void)hipFree(d_flag);
-    h->max_cell = maxlen;
-    FP_HIP_H(dalloc(h, &h->cell_box, 2 * (size_t)nnz));
-    if (nnz > 0) {
-        k_cellbox<<<(int)((nnz + 255) / 256), 256, 0, s>>>(h->bbox, h->cell_el, nnz, h->cell_box);
-        FP_HIP_H(hipGetLastError());
-    }
-    h->MC = std::max(1, maxlen);
-
-    // workspace
-    if ((double)max_points * (double)h->MC >= 2147483647.0) {
-        release(h);
-        set_error("findpts_setup: max_points x longest cell list exceeds 2^31; lower max_points");
-        return FP_ERANGE;
-    }
-    {
-        const size_t wb = work_bytes(E, h->MC, max_points, h->delta != nullptr);
-        FP_HIP_H(hipMalloc(&h->work_mem, wb));
-        h->bytes += wb;
-        work_carve(h->work, (char *)h->work_mem, E, h->MC, max_points, h->delta != nullptr);
+        return rc;
     }
     FP_HIP_H(hipStreamSynchronize(s));
     *out = h;
     return FP_OK;
+}
+
+extern "C" int findpts_update(fp_handle *h, const double *x, const double *y, const double *z,
+                              const double *delta, void *stream)
+{
+    if (!h || !x || !y || !z) {
+        set_error("findpts_update: NULL argument");
+        return FP_EINVAL;
+    }
+    if (delta && !h->delta) {
+        set_error("findpts_update: the handle was set up without a distance field");
+        return FP_ESTATE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    FP_HIP(hipGetDevice(&dev));
+    if (dev != h->device) FP_HIP(hipSetDevice(h->device));
+    if (delta)
+        FP_HIP(hipMemcpyAsync(h->delta, delta, sizeof(double) * (size_t)h->E * h->V,
+                              hipMemcpyDeviceToDevice, s));
+    int rc = build_geometry(h, x, y, z, s, "findpts_update");
+    if (rc == FP_OK) rc = ensure_workspace(h, "findpts_update");
+    return rc;
 }
 
 extern "C" int findpts_free(fp_handle *h)

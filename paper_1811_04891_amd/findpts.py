@@ -23,7 +23,7 @@ FP_INSIDE, FP_BORDER, FP_NOT_FOUND = 0, 1, 2
 FP_PREC_FP64, FP_PREC_MIXED = 0, 1
 
 # Every symbol the C ABI exports (checked against include/findpts.h by tests).
-SYMBOLS = ("findpts_setup", "findpts", "findpts_eval", "findpts_set_precision",
+SYMBOLS = ("findpts_setup", "findpts_update", "findpts", "findpts_eval", "findpts_set_precision",
            "findpts_stats", "findpts_timing", "findpts_timing_read",
            "findpts_get_bbox", "findpts_get_hash", "findpts_get_cells",
            "findpts_footprint", "findpts_free", "fp_last_error", "fp_copy",
@@ -52,6 +52,7 @@ def lib():
     vp, ip, dp, llp = C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_longlong)
     L.findpts_setup.argtypes = [C.POINTER(vp), vp, vp, vp, C.c_int, C.c_int, C.c_double,
                                 vp, vp, C.c_int, C.c_int, vp]
+    L.findpts_update.argtypes = [vp, vp, vp, vp, vp, vp]
     L.findpts.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp]
     L.findpts_eval.argtypes = [vp, C.c_int, vp, vp, vp, C.c_int, C.POINTER(vp), vp, vp]
     L.findpts_set_precision.argtypes = [vp, C.c_int]
@@ -144,6 +145,16 @@ def findpts_setup(x: torch.Tensor, y: torch.Tensor, z: torch.Tensor, N: int,
                              int(max_points), int(precision), _stream(stream))
     _check(rc, "findpts_setup")
     return Handle(h, E, N, x.device)
+
+
+def findpts_update(h: Handle, x: torch.Tensor, y: torch.Tensor, z: torch.Tensor,
+                   delta: Optional[torch.Tensor] = None, stream=None):
+    """New node coordinates of the same mesh (moving or deforming meshes)."""
+    n = h.E * h.V
+    _check(lib().findpts_update(h.ptr, _ptr(x, torch.float64, "x", n),
+                                _ptr(y, torch.float64, "y", n), _ptr(z, torch.float64, "z", n),
+                                _ptr(delta, torch.float64, "delta", n), _stream(stream)),
+           "findpts_update")
 
 
 def findpts(h: Handle, pts: torch.Tensor, pt_session: Optional[torch.Tensor] = None,
