@@ -645,11 +645,17 @@ static int build_geometry(fp_handle *h, const double *x, const double *y, const 
     return FP_OK;
 }
 
-// The handle's own workspace, (re)carved when the longest cell list grew.
+// The handle's own workspace, (re)carved when the longest cell list outgrew
+// it.  A quarter of headroom on the candidate slots lets a moving mesh whose
+// longest list changes by a little keep its workspace (a new allocation is
+// also touched for the first time by the next call, which costs tens of ms
+// for a workspace of a gigabyte).
 static int ensure_workspace(fp_handle *h, const char *who)
 {
     if (h->work_mem && h->MC <= h->work.MC) return FP_OK;
-    if ((double)h->max_points * (double)h->MC >= 2147483647.0) {
+    int mc_cap = h->MC + (h->MC + 3) / 4;
+    if ((double)h->max_points * (double)mc_cap >= 2147483647.0) mc_cap = h->MC;
+    if ((double)h->max_points * (double)mc_cap >= 2147483647.0) {
         set_error(std::string(who) +
                   ": max_points x longest cell list exceeds 2^31; lower max_points");
         return FP_ERANGE;
@@ -660,10 +666,10 @@ static int ensure_workspace(fp_handle *h, const char *who)
         h->bytes -= h->work_bytes;
         h->work_mem = nullptr;
     }
-    h->work_bytes = work_bytes(h->E, h->MC, h->max_points, h->delta != nullptr);
+    h->work_bytes = work_bytes(h->E, mc_cap, h->max_points, h->delta != nullptr);
     FP_HIP(hipMalloc(&h->work_mem, h->work_bytes));
     h->bytes += h->work_bytes;
-    work_carve(h->work, (char *)h->work_mem, h->E, h->MC, h->max_points, h->delta != nullptr);
+    work_carve(h->work, (char *)h->work_mem, h->E, mc_cap, h->max_points, h->delta != nullptr);
     return FP_OK;
 }
 
