@@ -207,6 +207,40 @@ FP_API const char *fp_last_error(void);
 FP_API int fp_copy(const void *src, void *dst, size_t bytes, void *stream);
 
 /*
+ * Interface data (what the Schwarz exchange does with interpolated values).
+ *
+ * fp_flux_correct -- mass-flux correction of boundary velocity data of one
+ * subdomain (Section 2.2, Eqs. 1-3): with F the boundary flux of the
+ * tentative velocity (sum of w_p u_p . n_p over all npts boundary points)
+ * and A the area of the interpolated part (sum of w_p n_p . n_p over the
+ * points with iface[p] != 0), gamma = -F / A (0 if A = 0) and
+ * u_p += gamma n_p on the interpolated points, so that the corrected data
+ * has zero net flux.
+ *   w      npts surface quadrature weights (area elements).
+ *   n      unit outward normals, component c of point p at n[c*ldn + p]
+ *          (ldn >= npts).
+ *   iface  npts ints (non-zero: interpolated point) or NULL (all are).
+ *   u      velocity, component c of point p at u[c*ldu + p] (ldu >= npts;
+ *          the layout findpts_eval writes, ldu = its npts, so that one
+ *          subdomain's points are a slice); corrected in place.
+ *   work   device buffer of FP_FLUX_WORK doubles; work[0] receives gamma.
+ * Sums in binary64 with a fixed reduction order (bit-reproducible).
+ * Allocates nothing.  Errors: FP_EINVAL.
+ *
+ * fp_extrapolate -- m-th order extrapolation in time of interface data
+ * (Section 2: lagged data extrapolated to order m, 1 <= m <= 3, constant time
+ * step): out = sum_q beta_q hist[q], weights (1), (2, -1), (3, -3, 1).
+ *   h_hist  HOST array of `order` device arrays of n doubles, most recent
+ *           first.  out may alias none of them.
+ */
+#define FP_FLUX_WORK 1024
+FP_API int fp_flux_correct(int npts, const double *w, const double *n, long long ldn,
+                           const int *iface, double *u, long long ldu, double *work,
+                           void *stream);
+FP_API int fp_extrapolate(long long n, int order, const double *const *h_hist, double *out,
+                          void *stream);
+
+/*
  * Serving layer.  Not a step of the paper's method: Section 2.1 runs one
  * findpts (and findpts_eval per field) per Schwarz exchange over all
  * interface points of a session; this layer serves many such calls, on many

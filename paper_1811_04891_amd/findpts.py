@@ -27,8 +27,11 @@ SYMBOLS = ("findpts_setup", "findpts_update", "findpts", "findpts_eval", "findpt
            "findpts_stats", "findpts_timing", "findpts_timing_read",
            "findpts_get_bbox", "findpts_get_hash", "findpts_get_cells",
            "findpts_footprint", "findpts_free", "fp_last_error", "fp_copy",
+           "fp_flux_correct", "fp_extrapolate",
            "fps_create", "fps_add_mesh", "fps_submit", "fps_wait", "fps_latency",
            "fps_destroy")
+
+FP_FLUX_WORK = 1024
 
 
 class FindptsError(RuntimeError):
@@ -67,6 +70,8 @@ def lib():
     L.fp_last_error.restype = C.c_char_p
     L.fp_last_error.argtypes = []
     L.fp_copy.argtypes = [vp, vp, C.c_size_t, vp]
+    L.fp_flux_correct.argtypes = [C.c_int, vp, vp, C.c_longlong, vp, vp, C.c_longlong, vp, vp]
+    L.fp_extrapolate.argtypes = [C.c_longlong, C.c_int, C.POINTER(vp), vp, vp]
     L.fps_create.argtypes = [C.POINTER(vp), C.c_size_t, C.c_int]
     L.fps_add_mesh.argtypes = [vp, vp, C.POINTER(vp), C.c_int, ip]
     L.fps_submit.argtypes = [vp, C.c_int, C.c_int, vp, vp, C.c_int, ip, vp, vp, vp, vp, vp, llp]
@@ -256,6 +261,42 @@ def fp_copy(src: torch.Tensor, dst: torch.Tensor, stream=None):
         raise ValueError("dst too small")
     _check(lib().fp_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
                          nbytes, _stream(stream)), "fp_copy")
+
+
+def fp_flux_correct(w: torch.Tensor, n: torch.Tensor, u: torch.Tensor,
+                    iface: Optional[torch.Tensor] = None, work: Optional[torch.Tensor] = None,
+                    stream=None) -> torch.Tensor:
+    """Mass-flux correction of u (3, P) in place; returns the work buffer
+    (work[0] = gamma).  n and u may be (3, P) views with a row stride (e.g.
+    a column slice of findpts_eval's output)."""
+    P = w.numel()
+    if work is None:
+        work = torch.empty(FP_FLUX_WORK, dtype=torch.float64, device=w.device)
+    for name, t in (("n", n), ("u", u)):
+        if (t.dim() != 2 or t.shape[0] < 3 or t.shape[1] != P or t.stride(1) != 1
+                or t.dtype != torch.float64 or t.device.type != "cuda"):
+            raise ValueError(f"{name} must be a (3, {P}) float64 CUDA tensor with unit column stride")
+    _check(lib().fp_flux_correct(int(P), _ptr(w, torch.float64, "w", P),
+                                 C.c_void_p(n.data_ptr()), C.c_longlong(n.stride(0)),
+                                 _ptr(iface, torch.int32, "iface", P),
+                                 C.c_void_p(u.data_ptr()), C.c_longlong(u.stride(0)),
+                                 _ptr(work, torch.float64, "work", FP_FLUX_WORK),
+                                 _stream(stream)), "fp_flux_correct")
+    return work
+
+
+def fp_extrapolate(hist: Sequence[torch.Tensor], order: int, out: Optional[torch.Tensor] = None,
+                   stream=None) -> torch.Tensor:
+    """m-th order time extrapolation; hist most recent first."""
+    n = hist[0].numel()
+    if out is None:
+        out = torch.empty_like(hist[0])
+    arr = (C.c_void_p * max(1, len(hist)))(
+        *[_ptr(t, torch.float64, f"hist[{i}]", n).value for i, t in enumerate(hist)])
+    _check(lib().fp_extrapolate(C.c_longlong(n), int(order), arr,
+                                _ptr(out, torch.float64, "out", n), _stream(stream)),
+           "fp_extrapolate")
+    return out
 
 
 class Request:

@@ -30,3 +30,30 @@ def dphi_np(x, y, z, amp=0.04):
         [amp * (z * z + 0.5 * z), 1 + amp * (-0.6 * y), amp * (2 * z * x + 0.5 * x)],
         [amp * (2 * x + 0.2 * y), amp * (-z * z + 0.2 * x), 1 + amp * (-2 * y * z)],
     ])
+
+
+def box_surface(lo, hi, N=4):
+    """GLL nodes on the 6 faces of an axis-aligned box: points (3, P),
+    weights (P,) = tensor GLL weights x face Jacobian, outward normals (3, P).
+    GLL quadrature of degree 2N-1 is exact for the low-degree fields of the
+    interface tests."""
+    import oracle
+    z, wq = oracle.gll(N)
+    pts, ws, ns = [], [], []
+    lo, hi = np.asarray(lo, float), np.asarray(hi, float)
+    for ax in range(3):
+        a, b = [d for d in range(3) if d != ax]
+        ja, jb = 0.5 * (hi[a] - lo[a]), 0.5 * (hi[b] - lo[b])
+        for side, val in ((-1.0, lo[ax]), (1.0, hi[ax])):
+            for i in range(N + 1):
+                for j in range(N + 1):
+                    p = np.zeros(3)
+                    p[ax] = val
+                    p[a] = lo[a] + ja * (z[i] + 1)
+                    p[b] = lo[b] + jb * (z[j] + 1)
+                    nn = np.zeros(3)
+                    nn[ax] = side
+                    pts.append(p)
+                    ws.append(wq[i] * wq[j] * ja * jb)
+                    ns.append(nn)
+    return np.array(pts).T, np.array(ws), np.array(ns).T

@@ -28,6 +28,8 @@ from .meshes import (  # noqa: F401
     queries_c3,
     queries_c5,
     c3_interface_nodes,
+    c3_interface_quadrature,
+    gll_weights,
     poly_fields,
     ref_poly_fields,
 )

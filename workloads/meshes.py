@@ -373,6 +373,58 @@ def c3_interface_nodes(mesh: Mesh):
     return torch.cat(pts).contiguous(), torch.cat(tags).contiguous()
 
 
+def gll_weights(N: int) -> np.ndarray:
+    """GLL quadrature weights 2 / (N (N+1) P_N(x_i)^2) at gll_points(N)."""
+    x = gll_points(N)
+    pn = np.polynomial.legendre.legval(x, [0.0] * N + [1.0])
+    return 2.0 / (N * (N + 1) * pn * pn)
+
+
+def c3_interface_quadrature(mesh: Mesh):
+    """The two-session interface of the overlap mesh as boundary quadrature
+    data: points, session tags, unit normals pointing out of the owning
+    session, and surface weights (tensor GLL weights times the face area / 4;
+    the faces of each kind all have the same area: 0.1 x 0.05 on the hole,
+    (2 pi / 50) x 0.05 on the cylinder).  Returns torch tensors
+    (pts (P, 3), tags (P,), normals (3, P), weights (P,))."""
+    N, eps = mesh.N, 1e-12
+    X, Y, Z, S = mesh.x, mesh.y, mesh.z, mesh.session
+    wq = torch.as_tensor(gll_weights(N), dtype=torch.float64, device=X.device)
+    w2 = (wq[:, None] * wq[None, :]) / 4.0
+    slices = [(Ellipsis, 0), (Ellipsis, N), (slice(None), slice(None), 0),
+              (slice(None), slice(None), N), (slice(None), 0), (slice(None), N)]
+    pts, tags, nrm, wts = [], [], [], []
+    for sl in slices:
+        fx, fy, fz = X[sl], Y[sl], Z[sl]
+        ax, ay = fx.abs(), fy.abs()
+        on_x = ((ax - 0.55).abs() < eps).all(dim=(1, 2)) & (ay <= 0.55 + eps).all(dim=(1, 2))
+        on_y = ((ay - 0.55).abs() < eps).all(dim=(1, 2)) & (ax <= 0.55 + eps).all(dim=(1, 2))
+        rho = torch.sqrt(fx * fx + fy * fy)
+        on_r = ((rho - 1.0).abs() < 1e-12).all(dim=(1, 2))
+        for sel, tag, kind in (((on_x & (S == 0)), 0, "x"), ((on_y & (S == 0)), 0, "y"),
+                               ((on_r & (S == 1)), 1, "r")):
+            if not bool(sel.any()):
+                continue
+            px, py, pz = fx[sel], fy[sel], fz[sel]
+            P = torch.stack([px, py, pz], -1).reshape(-1, 3)
+            if kind == "x":      # hole face: the box session lies away from the hole
+                nv = torch.stack([-torch.sign(px), 0 * px, 0 * px], 0)
+                area = 0.1 * 0.05
+            elif kind == "y":
+                nv = torch.stack([0 * py, -torch.sign(py), 0 * py], 0)
+                area = 0.1 * 0.05
+            else:                # outer cylinder of the annulus session
+                r = torch.sqrt(px * px + py * py)
+                nv = torch.stack([px / r, py / r, 0 * px], 0)
+                area = (2.0 * math.pi / 50.0) * 0.05
+            pts.append(P)
+            tags.append(torch.full((P.shape[0],), tag, dtype=torch.int32, device=P.device))
+            nrm.append(nv.reshape(3, -1))
+            wts.append((area * w2).expand(px.shape).reshape(-1))
+    return (torch.cat(pts).contiguous(), torch.cat(tags).contiguous(),
+            torch.cat(nrm, dim=1).contiguous(), torch.cat(wts).contiguous())
+
+
 # --------------------------------------------------------------------------
 # Nodal fields.
 # --------------------------------------------------------------------------
