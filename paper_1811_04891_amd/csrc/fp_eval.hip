@@ -1,7 +1,8 @@
 // findpts_eval: tensor-product Lagrange interpolation of nodal fields at
 // located points (Section 2.1 of the paper).  Points are grouped by element
-// with a counting sort so that one 64-lane wavefront reads each element's
-// field values once (scalar loads) for all of its points.
+// with a counting sort so that one 64-lane wavefront reads an element's field
+// values once (scalar loads) for a run of its points (a work unit; an element
+// with many points is spread over several units).
 #include <cmath>
 
 #include "fp_basis.h"
@@ -53,31 +54,38 @@ __global__ __launch_bounds__(256) void k_ev_scatter(EvArgs a)
     if (k >= 0) a.order[a.off[a.el[p]] + k] = p;
 }
 
+// One wavefront per work unit: up to kUnitEval points of one element, 64 at a
+// time, field rows through scalar loads.
+constexpr int kUnitEval = 256;
+
 template <int N1>
 __global__ __launch_bounds__(kWave) void k_eval(EvArgs a, FieldPtrs F, const double *__restrict__ basis)
 {
     constexpr int V = N1 * N1 * N1;
     const BasisPtr<double> B{as_const(basis)};
-    const int e = blockIdx.x;
-    const int beg = a.off[e], end = a.off[e + 1];
-    if (beg >= end) return;
-    for (int base = beg; base < end; base += kWave) {
-        const int q = base + (int)threadIdx.x;
-        const bool act = q < end;
-        const int p = act ? a.order[q] : 0;
-        double r0 = 0.0, r1 = 0.0, r2 = 0.0;
-        if (act) {
-            r0 = a.rst[3 * (long long)p];
-            r1 = a.rst[3 * (long long)p + 1];
-            r2 = a.rst[3 * (long long)p + 2];
-        }
-        double hr[N1], hs[N1], ht[N1];
-        lagrange<N1>(B, r0, hr);
-        lagrange<N1>(B, r1, hs);
-        lagrange<N1>(B, r2, ht);
-        for (int f = 0; f < a.nf; ++f) {
-            const double v = field_value<N1>(as_const(F.f[f] + (long long)e * V), hr, hs, ht);
-            if (act) a.out[f * a.ostride + p] = v;
+    const long long nu = unit_end(a.off, a.E, a.E, kUnitEval);
+    for (long long unit = blockIdx.x; unit < nu; unit += gridDim.x) {
+        Unit U;
+        if (!unit_at(unit, a.off, a.E, 1, a.E, kUnitEval, U)) continue;
+        const int e = U.seg, beg = U.beg, end = U.end;
+        for (int base = beg; base < end; base += kWave) {
+            const int q = base + (int)threadIdx.x;
+            const bool act = q < end;
+            const int p = act ? a.order[q] : 0;
+            double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+            if (act) {
+                r0 = a.rst[3 * (long long)p];
+                r1 = a.rst[3 * (long long)p + 1];
+                r2 = a.rst[3 * (long long)p + 2];
+            }
+            double hr[N1], hs[N1], ht[N1];
+            lagrange<N1>(B, r0, hr);
+            lagrange<N1>(B, r1, hs);
+            lagrange<N1>(B, r2, ht);
+            for (int f = 0; f < a.nf; ++f) {
+                const double v = field_value<N1>(as_const(F.f[f] + (long long)e * V), hr, hs, ht);
+                if (act) a.out[f * a.ostride + p] = v;
+            }
         }
     }
 }
@@ -99,11 +107,12 @@ struct FieldAcc {
 };
 
 // Element groups staged in LDS, one field at a time.  A 256-thread block
-// owns G consecutive elements and all their points (contiguous in the
-// element-grouped order); for each field it stages the G element blocks
+// takes a work unit: G consecutive elements and a run of up to kUnitGrp of
+// their points (contiguous in the element-grouped order); for each field it stages the G element blocks
 // (padded by 16 bytes so lanes on different elements use different LDS
 // banks) and every thread interpolates its points.
 constexpr int kEvThreads = 256;
+constexpr int kUnitGrp = 1024;  // points of one element group per work unit
 
 template <int N1>
 struct EvGroup {
@@ -121,34 +130,39 @@ __global__ __launch_bounds__(kEvThreads) void k_eval_grp(EvArgs a, FieldPtrs F,
     constexpr int V = Gr::V, G = Gr::G, S = Gr::stride;
     __shared__ double sF[G * S];
     const BasisPtr<double> B{as_const(basis)};
-    const int e0 = blockIdx.x * G;
-    const int ne = min(G, a.E - e0);
-    const int pb = a.off[e0], pe = a.off[e0 + ne];
-    if (pe <= pb) return;  // uniform across the block
-    for (int f = 0; f < a.nf; ++f) {
-        const double *src = F.f[f] + (long long)e0 * V;
-        for (int q = threadIdx.x; q < ne * V; q += kEvThreads) {
-            const int g = q / V;
-            sF[g * S + (q - g * V)] = src[q];
+    const int ns = (a.E + G - 1) / G;
+    const long long nu = unit_end(a.off, ns, a.E, kUnitGrp);
+    for (long long unit = blockIdx.x; unit < nu; unit += gridDim.x) {
+        Unit U;
+        if (!unit_at(unit, a.off, ns, G, a.E, kUnitGrp, U)) continue;  // uniform
+        const int e0 = U.seg * G;
+        const int ne = min(G, a.E - e0);
+        const int pb = U.beg, pe = U.end;
+        for (int f = 0; f < a.nf; ++f) {
+            const double *src = F.f[f] + (long long)e0 * V;
+            for (int q = threadIdx.x; q < ne * V; q += kEvThreads) {
+                const int g = q / V;
+                sF[g * S + (q - g * V)] = src[q];
+            }
+            __syncthreads();
+            for (int u = pb + threadIdx.x; u < pe; u += kEvThreads) {
+                const int p = a.order[u];
+                const int g = a.el[p] - e0;
+                FieldAcc<N1> acc;
+                lagrange<N1>(B, a.rst[3 * (long long)p], acc.hr);
+                lagrange<N1>(B, a.rst[3 * (long long)p + 1], acc.hs);
+                lagrange<N1>(B, a.rst[3 * (long long)p + 2], acc.ht);
+                double buf[kPrefetch + 1][N1];
+                walk_rows<N1, 1, 0>((lptr<double>)(sF + g * S), buf, acc);
+                a.out[f * a.ostride + p] = acc.v;
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        for (int u = pb + threadIdx.x; u < pe; u += kEvThreads) {
-            const int p = a.order[u];
-            const int g = a.el[p] - e0;
-            FieldAcc<N1> acc;
-            lagrange<N1>(B, a.rst[3 * (long long)p], acc.hr);
-            lagrange<N1>(B, a.rst[3 * (long long)p + 1], acc.hs);
-            lagrange<N1>(B, a.rst[3 * (long long)p + 2], acc.ht);
-            double buf[kPrefetch + 1][N1];
-            walk_rows<N1, 1, 0>((lptr<double>)(sF + g * S), buf, acc);
-            a.out[f * a.ostride + p] = acc.v;
-        }
-        __syncthreads();
     }
 }
 
-// Interpolation on the matrix cores (orders 1..7): one wavefront per element,
-// its points in batches of 16.  For field f the first contraction
+// Interpolation on the matrix cores (orders 1..7): one wavefront per work
+// unit (up to kUnitEvalMfma points of one element), points in batches of 16.  For field f the first contraction
 // a_f(k, j; point) = sum_i F_f[k][j][i] h_i(r_point) is a dense product of the
 // field's rows (n1^2 x n1) with the basis values of 16 points, one
 // v_mfma_f64_16x16x4f64 per 16 rows and 4 i-values; the field's A fragments
@@ -157,6 +171,7 @@ __global__ __launch_bounds__(kEvThreads) void k_eval_grp(EvArgs a, FieldPtrs F,
 // h_j(s) and every plane k with h_k(t), and the 4 lanes of point n add their
 // partial sums (same order in all 4: the total is bit-identical).
 constexpr int kEvFieldsPerPass = 4;
+constexpr int kUnitEvalMfma = 512;  // points of one element per work unit
 
 template <int N1>
 __global__ __launch_bounds__(kWave) void k_eval_mfma(EvArgs a, FieldPtrs F,
@@ -167,87 +182,91 @@ __global__ __launch_bounds__(kWave) void k_eval_mfma(EvArgs a, FieldPtrs F,
     constexpr int MBF = (N1 + S::PPB - 1) / S::PPB;  // M blocks per field (planes k)
     constexpr int NF = kEvFieldsPerPass;
     const BasisPtr<double> B{as_const(basis)};
-    const int e = blockIdx.x;
-    const int beg = a.off[e], end = a.off[e + 1];
-    if (beg >= end) return;
-    const int lane = threadIdx.x, n = lane & 15, g = lane >> 4;
-    // A fragment coordinates of this lane: row -> plane p, row jj; column i
-    const int row = lane & 15, q = lane >> 4;
-    const int gr = MF<double>::grp(row), vr = MF<double>::comp(row);
-    const int pr = vr / S::EPP, jj = gr + 4 * (vr % S::EPP);
-    for (int f0 = 0; f0 < a.nf; f0 += NF) {
-        double A[NF][MBF][S::KB];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            const double *src = (f0 + f < a.nf) ? F.f[f0 + f] + (long long)e * V : nullptr;
-#pragma unroll
-            for (int mb = 0; mb < MBF; ++mb) {
-                const int k = mb * S::PPB + pr;
-#pragma unroll
-                for (int kb = 0; kb < S::KB; ++kb) {
-                    const int i = 4 * kb + q;
-                    const bool ok = src && k < N1 && jj < N1 && i < N1;
-                    A[f][mb][kb] = ok ? src[N1 * (jj + N1 * k) + i] : 0.0;
-                }
-            }
-        }
-        for (int b0 = beg; b0 < end; b0 += 16) {
-            const int u = b0 + n;
-            const bool act = u < end;
-            const int p = a.order[act ? u : beg];
-            double hr[N1], hs[N1], ht[N1];
-            lagrange<N1>(B, a.rst[3 * (long long)p], hr);
-            lagrange<N1>(B, a.rst[3 * (long long)p + 1], hs);
-            lagrange<N1>(B, a.rst[3 * (long long)p + 2], ht);
-            double hrl[S::KB], hsl[S::EPP];
-#pragma unroll
-            for (int w = 0; w < S::KB; ++w) {
-                double vr_ = 0.0, vs_ = 0.0;
-#pragma unroll
-                for (int gg = 0; gg < 4; ++gg) {
-                    const int i = gg + 4 * w;
-                    if (i < N1) {
-                        vr_ = (g == gg) ? hr[i] : vr_;
-                        vs_ = (g == gg) ? hs[i] : vs_;
+    const long long nu = unit_end(a.off, a.E, a.E, kUnitEvalMfma);
+    for (long long unit = blockIdx.x; unit < nu; unit += gridDim.x) {
+        Unit U;
+        if (!unit_at(unit, a.off, a.E, 1, a.E, kUnitEvalMfma, U)) continue;
+        const int e = U.seg, beg = U.beg, end = U.end;
+        const int lane = threadIdx.x, n = lane & 15, g = lane >> 4;
+        // A fragment coordinates of this lane: row -> plane p, row jj; column i
+        const int row = lane & 15, q = lane >> 4;
+        const int gr = MF<double>::grp(row), vr = MF<double>::comp(row);
+        const int pr = vr / S::EPP, jj = gr + 4 * (vr % S::EPP);
+        for (int f0 = 0; f0 < a.nf; f0 += NF) {
+            double A[NF][MBF][S::KB];
+    #pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const double *src = (f0 + f < a.nf) ? F.f[f0 + f] + (long long)e * V : nullptr;
+    #pragma unroll
+                for (int mb = 0; mb < MBF; ++mb) {
+                    const int k = mb * S::PPB + pr;
+    #pragma unroll
+                    for (int kb = 0; kb < S::KB; ++kb) {
+                        const int i = 4 * kb + q;
+                        const bool ok = src && k < N1 && jj < N1 && i < N1;
+                        A[f][mb][kb] = ok ? src[N1 * (jj + N1 * k) + i] : 0.0;
                     }
                 }
-                hrl[w] = vr_;
-                hsl[w] = vs_;
             }
-#pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                if (f0 + f < a.nf) {
-                    double v = 0.0;
-#pragma unroll
-                    for (int mb = 0; mb < MBF; ++mb) {
-                        dx4 c = {0, 0, 0, 0};
-#pragma unroll
-                        for (int kb = 0; kb < S::KB; ++kb)
-                            c = MF<double>::mma(A[f][mb][kb], hrl[kb], c);
-#pragma unroll
-                        for (int pp = 0; pp < S::PPB; ++pp) {
-                            const int k = mb * S::PPB + pp;
-                            if (k < N1) {
-                                double sa = 0.0;
-#pragma unroll
-                                for (int w = 0; w < S::EPP; ++w)
-                                    sa = fma(c[pp * S::EPP + w], hsl[w], sa);
-                                v = fma(sa, ht[k], v);
-                            }
+            for (int b0 = beg; b0 < end; b0 += 16) {
+                const int u = b0 + n;
+                const bool act = u < end;
+                const int p = a.order[act ? u : beg];
+                double hr[N1], hs[N1], ht[N1];
+                lagrange<N1>(B, a.rst[3 * (long long)p], hr);
+                lagrange<N1>(B, a.rst[3 * (long long)p + 1], hs);
+                lagrange<N1>(B, a.rst[3 * (long long)p + 2], ht);
+                double hrl[S::KB], hsl[S::EPP];
+    #pragma unroll
+                for (int w = 0; w < S::KB; ++w) {
+                    double vr_ = 0.0, vs_ = 0.0;
+    #pragma unroll
+                    for (int gg = 0; gg < 4; ++gg) {
+                        const int i = gg + 4 * w;
+                        if (i < N1) {
+                            vr_ = (g == gg) ? hr[i] : vr_;
+                            vs_ = (g == gg) ? hs[i] : vs_;
                         }
                     }
-                    v = slot_sum(v);
-                    if (act && g == 0) a.out[(f0 + f) * a.ostride + p] = v;
+                    hrl[w] = vr_;
+                    hsl[w] = vs_;
+                }
+    #pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    if (f0 + f < a.nf) {
+                        double v = 0.0;
+    #pragma unroll
+                        for (int mb = 0; mb < MBF; ++mb) {
+                            dx4 c = {0, 0, 0, 0};
+    #pragma unroll
+                            for (int kb = 0; kb < S::KB; ++kb)
+                                c = MF<double>::mma(A[f][mb][kb], hrl[kb], c);
+    #pragma unroll
+                            for (int pp = 0; pp < S::PPB; ++pp) {
+                                const int k = mb * S::PPB + pp;
+                                if (k < N1) {
+                                    double sa = 0.0;
+    #pragma unroll
+                                    for (int w = 0; w < S::EPP; ++w)
+                                        sa = fma(c[pp * S::EPP + w], hsl[w], sa);
+                                    v = fma(sa, ht[k], v);
+                                }
+                            }
+                        }
+                        v = slot_sum(v);
+                        if (act && g == 0) a.out[(f0 + f) * a.ostride + p] = v;
+                    }
                 }
             }
         }
     }
 }
 
-static hipError_t launch_eval_kernel(int n1, int E, const EvArgs &a, const FieldPtrs &F,
+// Launches the order's interpolation kernel over the work units of n points.
+static hipError_t launch_eval_kernel(int n1, int E, int n, const EvArgs &a, const FieldPtrs &F,
                                      const double *B, hipStream_t s)
 {
-#define FP_LAUNCH_MFMA(N1) k_eval_mfma<N1><<<E, kWave, 0, s>>>(a, F, B)
+#define FP_LAUNCH_MFMA(N1) k_eval_mfma<N1><<<unit_grid(E, n, kUnitEvalMfma), kWave, 0, s>>>(a, F, B)
     switch (n1) {
         case 2: FP_LAUNCH_MFMA(2); return hipGetLastError();
         case 3: FP_LAUNCH_MFMA(3); return hipGetLastError();
@@ -259,15 +278,16 @@ static hipError_t launch_eval_kernel(int n1, int E, const EvArgs &a, const Field
         default: break;
     }
 #undef FP_LAUNCH_MFMA
-#define FP_LAUNCH_GRP(N1) \
-    k_eval_grp<N1><<<(E + EvGroup<N1>::G - 1) / EvGroup<N1>::G, kEvThreads, 0, s>>>(a, F, B)
+#define FP_LAUNCH_GRP(N1)                                                                 \
+    k_eval_grp<N1><<<unit_grid((E + EvGroup<N1>::G - 1) / EvGroup<N1>::G, n, kUnitGrp),   \
+                     kEvThreads, 0, s>>>(a, F, B)
     switch (n1) {
         case 9: FP_LAUNCH_GRP(9); return hipGetLastError();
         case 10: FP_LAUNCH_GRP(10); return hipGetLastError();
         default: break;
     }
 #undef FP_LAUNCH_GRP
-#define FP_LAUNCH_EVAL(N1) k_eval<N1><<<E, kWave, 0, s>>>(a, F, B)
+#define FP_LAUNCH_EVAL(N1) k_eval<N1><<<unit_grid(E, n, kUnitEval), kWave, 0, s>>>(a, F, B)
     switch (n1) {
         case 2: FP_LAUNCH_EVAL(2); break;
         case 3: FP_LAUNCH_EVAL(3); break;
@@ -333,7 +353,7 @@ int run_eval(fp_handle *h, const Work &w, int npts, const int *code, const int *
                 FP_HIP(hipGetLastError());
                 if (timed) FP_HIP(hipEventRecord(l0, s));
             }
-            FP_HIP(launch_eval_kernel(h->n1, h->E, a, F, h->d_basis, s));
+            FP_HIP(launch_eval_kernel(h->n1, h->E, n, a, F, h->d_basis, s));
         }
         if (timed) {
             FP_HIP(hipEventRecord(l1, s));

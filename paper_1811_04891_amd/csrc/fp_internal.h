@@ -60,7 +60,7 @@ struct Work {
     int *redo = nullptr;      // M: second-pass flag per point
     int *scan_tmp = nullptr;  // block sums of the device scans
     unsigned *cand_part = nullptr;  // ceil(M / 256): per-block candidate counts
-    unsigned *iter_part = nullptr;  // E: Newton iterations per element
+    unsigned *iter_part = nullptr;  // unit_grid(E, M, kUnitMin): Newton iterations per block
     int *ev_cnt = nullptr;    // E + 1
     int *ev_off = nullptr;    // E + 1
     int *ev_pos = nullptr;    // M
@@ -139,6 +139,56 @@ hipEvent_t pool_event(fp_handle *h);
         hipError_t e_ = (call);                              \
         if (e_ != hipSuccess) return fp::hip_fail(e_, #call); \
     } while (0)
+
+// Work units of an element-grouped list.  Segment s (a run of gs consecutive
+// elements, s < ns) owns list positions [b(s), b(s + 1)) with
+// b(s) = off[min(s gs, ne)]; it is cut at the multiples of K and its piece in
+// window j (positions [j K, (j + 1) K)) is unit s + j.  Along the list both s
+// and j never decrease and at least one of them grows from one piece to the
+// next, so the unit indices of the pieces are distinct and increasing, and
+// the segment holding unit u is the last s with s + b(s) / K <= u.  A block
+// takes units blockIdx.x, blockIdx.x + gridDim.x, ... below unit_end(): an
+// element with many points is spread over many blocks, an empty one costs a
+// search.  Units of gaps (empty segments, cuts that fall on a segment's
+// start) are empty.
+struct Unit {
+    int seg, beg, end;
+};
+
+__device__ __forceinline__ long long unit_end(const int *off, int ns, int ne, int K)
+{
+    return (long long)ns + off[ne] / K + 1;
+}
+
+__device__ __forceinline__ bool unit_at(long long u, const int *off, int ns, int gs, int ne,
+                                        int K, Unit &U)
+{
+    auto b = [&](long long s) { return off[s * gs < ne ? s * gs : ne]; };
+    int lo = 0, hi = ns - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (mid + b(mid) / K <= u)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int b0 = b(lo), b1 = b(lo + 1);
+    const long long j = u - lo;
+    if (b0 >= b1 || j * K >= b1) return false;
+    U.seg = lo;
+    U.beg = (int)(j * K > b0 ? j * K : b0);
+    U.end = (int)((j + 1) * K < b1 ? (j + 1) * K : b1);
+    return true;
+}
+
+// Blocks of a unit launch over ns segments for a list of at most about
+// 2 n entries.  Pieces beyond the grid are taken by the grid-stride walk.
+inline int unit_grid(int ns, long long n, int K)
+{
+    const long long g = (long long)ns + 2 * ((n + K - 1) / K);
+    return (int)(g < 1 ? 1 : (g > 0x7fffffffLL ? 0x7fffffffLL : g));
+}
+constexpr int kUnitMin = 64;  // smallest K of the locate kernels
 
 // Exclusive scan of n ints: out[0..n], out[n] = total.  tmp needs
 // scan_tmp_size(n) ints.

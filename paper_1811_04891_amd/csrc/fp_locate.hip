@@ -11,11 +11,11 @@
 //              (ascending element ids) and each pair's rank in its element
 //   scan       pair counts per element -> element offsets
 //   k_scatter  pair slots grouped by element
-//   k_locate_mfma  (orders 1..7) one wavefront per element, element block in
-//              LDS, map and Jacobian of 16 pairs at a time on the matrix
-//              cores (fp_mfma.inc)
-//   k_locate   (orders 8..15) one wavefront per element, lanes = pairs of
-//              that element, node rows through scalar loads
+//   k_locate_mfma  (orders 1..7) one wavefront per work unit (a run of one
+//              element's pairs), element block in LDS, map and Jacobian of 16
+//              pairs at a time on the matrix cores (fp_mfma.inc)
+//   k_locate   (orders 8..15) one wavefront per work unit of 64 pairs,
+//              lanes = pairs, node rows through scalar loads
 //   k_select   per point: classification and owner rule, caller's order
 #include <cmath>
 
@@ -48,12 +48,13 @@ struct LocArgs {
     int *cand_pos;
     int *elem_cnt;
     const int *elem_off;
+    int E;
     int *order;
     double *res;
     double *res_dl;
     int *res_in;
     unsigned *cand_part;  // per k_cand block: the method's candidates (first pass)
-    unsigned *iter_part;  // per element: Newton iterations of its pairs
+    unsigned *iter_part;  // per block: Newton iterations of its pairs
 };
 
 __device__ __forceinline__ int cell_of(const Grid &g, int a, double x)
@@ -365,31 +366,29 @@ __device__ __forceinline__ void store_pair(const LocArgs &a, BasisPtr<double> B,
     }
 }
 
-// One 64-lane wavefront per element, lanes over its pairs, node rows from the
-// scalar cache (orders 8 and above, whose matrix-core fragments would not fit
-// in registers).
+// One 64-lane wavefront per work unit (up to 64 pairs of one element), lanes
+// over its pairs, node rows from the scalar cache (orders 8 and above, whose
+// matrix-core fragments would not fit in registers).
+constexpr int kUnitScalar = 64;
+
 template <int N1>
 __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__restrict__ basis)
 {
     constexpr int V = N1 * N1 * N1;
     const BasisPtr<double> B{as_const(basis)};
-    const int e = blockIdx.x;
-    const int beg = a.elem_off[e], end = a.elem_off[e + 1];
-    if (beg >= end) {
-        if (threadIdx.x == 0) a.iter_part[e] = 0;
-        return;
-    }
-    cptr<double> X = as_const(a.geom + (long long)e * 3 * V);
-    const double he = a.esize[e];
-    const double rstop = (kResidStop * he) * (kResidStop * he);
     unsigned long long my_iters = 0;
-
-    for (int base = beg; base < end; base += kWave) {
-        const int q = base + (int)threadIdx.x;
-        const bool act = q < end;
+    const long long nu = unit_end(a.elem_off, a.E, a.E, kUnitScalar);
+    for (long long u = blockIdx.x; u < nu; u += gridDim.x) {
+        Unit U;
+        if (!unit_at(u, a.elem_off, a.E, 1, a.E, kUnitScalar, U)) continue;
+        const int e = U.seg;
+        cptr<double> X = as_const(a.geom + (long long)e * 3 * V);
+        const double he = a.esize[e];
+        const double rstop = (kResidStop * he) * (kResidStop * he);
+        const int q = U.beg + (int)threadIdx.x;
+        const bool act = q < U.end;
         const int slot = act ? a.order[q] : 0;
-        const int tk = slot % a.M;
-        const int p = tk;
+        const int p = slot % a.M;
         double xs[3] = {0.0, 0.0, 0.0};
         if (act) {
             xs[0] = a.pts[3 * (long long)p];
@@ -426,7 +425,7 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
     // wave totals -> counters
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) my_iters += __shfl_xor(my_iters, o, kWave);
-    if (threadIdx.x == 0) a.iter_part[e] = (unsigned)my_iters;
+    if (threadIdx.x == 0) a.iter_part[blockIdx.x] = (unsigned)my_iters;
 }
 
 #include "fp_mfma.inc"
@@ -434,14 +433,14 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
 // Fold one pass's partial counts into the handle's counters: one block, so
 // the counters see a handful of atomics per pass.
 __global__ __launch_bounds__(1024) void k_stats(const unsigned *cand_part, int nb,
-                                                const unsigned *iter_part, int E,
+                                                const unsigned *iter_part, int ni, int E,
                                                 const int *elem_off, long long located,
                                                 unsigned long long *stats)
 {
     __shared__ unsigned long long sc[1024 / kWave], si[1024 / kWave];
     unsigned long long c = 0, it = 0;
     for (int i = threadIdx.x; i < nb; i += blockDim.x) c += cand_part[i];
-    for (int i = threadIdx.x; i < E; i += blockDim.x) it += iter_part[i];
+    for (int i = threadIdx.x; i < ni; i += blockDim.x) it += iter_part[i];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         c += __shfl_xor(c, o, kWave);
@@ -563,16 +562,26 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
         default: return hipErrorInvalidValue; \
     }
 
-static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, hipStream_t s)
+// Launches the order's Newton kernel over the work units of the pass's pairs
+// (n points); *nblk receives the grid size (one iteration partial per block).
+static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, int n,
+                                       hipStream_t s, int *nblk)
 {
-#define FP_LAUNCH_LOCATE(N1) k_locate<N1><<<h->E, kWave, 0, s>>>(a, h->d_basis)
+#define FP_LAUNCH_LOCATE(N1)                                      \
+    do {                                                          \
+        *nblk = unit_grid(h->E, n, kUnitScalar);                  \
+        k_locate<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis);      \
+    } while (0)
 // mixed precision: first pass only (the second pass is binary64)
-#define FP_LAUNCH_MFMA(N1)                                                          \
-    do {                                                                            \
-        if (h->precision == FP_PREC_MIXED && a.obb)                                 \
-            k_locate_mixed<N1><<<h->E, kWave, 0, s>>>(a, h->d_basis, h->d_basis32); \
-        else                                                                        \
-            k_locate_mfma<N1><<<h->E, kWave, 0, s>>>(a, h->d_basis);                \
+#define FP_LAUNCH_MFMA(N1)                                                           \
+    do {                                                                             \
+        if (h->precision == FP_PREC_MIXED && a.obb) {                                \
+            *nblk = unit_grid(h->E, n, kUnitMixed);                                  \
+            k_locate_mixed<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_basis32); \
+        } else {                                                                     \
+            *nblk = unit_grid(h->E, n, kUnitMfma);                                   \
+            k_locate_mfma<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis);                \
+        }                                                                            \
     } while (0)
     switch (h->n1) {
         case 2: FP_LAUNCH_MFMA(2); break;
@@ -632,6 +641,7 @@ int run_findpts(fp_handle *h, const Work &w, int npts, const double *pts, const 
         a.cand_pos = w.cand_pos;
         a.elem_cnt = w.elem_cnt;
         a.elem_off = w.elem_off;
+        a.E = h->E;
         a.order = w.order;
         a.res = w.res;
         a.res_dl = h->delta ? w.res_dl : nullptr;
@@ -662,11 +672,13 @@ int run_findpts(fp_handle *h, const Work &w, int npts, const double *pts, const 
         k_scatter<<<pb, 256, 0, s>>>(a);
         FP_HIP(hipGetLastError());
         if (timed) FP_HIP(hipEventRecord(l0, s));
-        FP_HIP(launch_locate_kernel(h, a, s));
+        int nblk = 0;
+        FP_HIP(launch_locate_kernel(h, a, n, s, &nblk));
         if (timed) FP_HIP(hipEventRecord(l1, s));
         k_select<<<pb, 256, 0, s>>>(a, co, eo, ro, dO);
         FP_HIP(hipGetLastError());
-        k_stats<<<1, 1024, 0, s>>>(w.cand_part, pb, w.iter_part, h->E, w.elem_off, n, h->stats);
+        k_stats<<<1, 1024, 0, s>>>(w.cand_part, pb, w.iter_part, nblk, h->E, w.elem_off, n,
+                                   h->stats);
         FP_HIP(hipGetLastError());
         // second pass over the flagged tasks with the axis-aligned candidates
         // only (other tasks get no candidates and keep their result)
@@ -679,10 +691,11 @@ int run_findpts(fp_handle *h, const Work &w, int npts, const double *pts, const 
         FP_HIP(scan_exclusive(w.elem_cnt, w.elem_off, h->E, w.scan_tmp, s));
         k_scatter<<<pb, 256, 0, s>>>(a);
         FP_HIP(hipGetLastError());
-        FP_HIP(launch_locate_kernel(h, a, s));
+        FP_HIP(launch_locate_kernel(h, a, n, s, &nblk));
         k_select<<<pb, 256, 0, s>>>(a, co, eo, ro, dO);
         FP_HIP(hipGetLastError());
-        k_stats<<<1, 1024, 0, s>>>(w.cand_part, 0, w.iter_part, h->E, w.elem_off, 0, h->stats);
+        k_stats<<<1, 1024, 0, s>>>(w.cand_part, 0, w.iter_part, nblk, h->E, w.elem_off, 0,
+                                   h->stats);
         FP_HIP(hipGetLastError());
         if (timed) {
             FP_HIP(hipEventRecord(t1, s));

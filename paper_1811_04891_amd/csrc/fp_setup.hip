@@ -475,7 +475,7 @@ void lay_out(Layout &L, Work &w, int E, int MC, int M, bool delta)
     w.redo = L.take<int>(m);
     w.scan_tmp = L.take<int>((size_t)scan_tmp_size((long long)E + 1));
     w.cand_part = L.take<unsigned>((m + 255) / 256);
-    w.iter_part = L.take<unsigned>((size_t)E);
+    w.iter_part = L.take<unsigned>((size_t)unit_grid(E, M, kUnitMin));
     w.ev_cnt = L.take<int>(e1);
     w.ev_off = L.take<int>(e1);
     w.ev_pos = L.take<int>(m);
