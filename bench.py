@@ -14,6 +14,8 @@ Prints one JSON line.  Besides the throughput it reports:
                 launch stream) vs 78.6 TFLOP/s; HBM traffic from the committed
                 hardware-counter summary when it was taken on this source
   cpu_baseline  the CPU oracle timed on a bounded sample of the same points
+  spiral        the N = 15 spiral element at tol 1e-14: 1000 points (the
+                paper's robustness case) and 1e6 points
   serving       a stream of requests on 16 resident meshes through the
                 serving layer: saturated throughput and p50/p99 latency at
                 0.5, 0.8 and 0.95 of the saturated request rate
@@ -264,6 +266,39 @@ def schwarz_bench(fp, w, dev, precision, steps=10, kappa=4):
     return res
 
 
+def spiral_bench(fp, w, dev, reps=20):
+    """Section 3.1 robustness case: one N = 15 spiral element, 1000 points
+    x^e(r) for random r, tol = 1e-14; the points are produced on the device by
+    interpolating the coordinate fields at (el 0, r).  Also the same call on
+    1e6 such points (the N = 15 Newton throughput)."""
+    import numpy as np
+    import torch
+    mesh = w.spiral_element(device=dev)
+    h = fp.findpts_setup(mesh.x, mesh.y, mesh.z, mesh.N, tol=1e-14, max_points=1 << 20)
+    out = {"element": "N=15 spiral, 1.5 turns", "tol": 1e-14}
+    for P in (1000, 1_000_000):
+        g = torch.Generator(device="cpu").manual_seed(21)
+        r = (torch.rand((P, 3), generator=g, dtype=torch.float64) * 2 - 1).to(dev)
+        zero = torch.zeros(P, dtype=torch.int32, device=dev)
+        pts = fp.findpts_eval(h, zero, zero, r, [mesh.x, mesh.y, mesh.z]).t().contiguous()
+        for _ in range(3):
+            code, el, rst, d2 = fp.findpts(h, pts)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps if P <= 1000 else 5):
+            t0 = time.perf_counter()
+            code, el, rst, d2 = fp.findpts(h, pts)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        c = np.bincount(code.cpu().numpy(), minlength=3).tolist()
+        dr = float((rst - r).abs().max())
+        out[f"P{P}"] = {"ms_per_call_median": 1e3 * float(np.median(ts)),
+                        "points_per_s": P / float(np.median(ts)), "codes": c,
+                        "max_abs_r_error": dr}
+    h.free()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -462,6 +497,8 @@ def main():
             "method_newton_iters_per_candidate": cb["K"],
         }
     h.free()
+    rec["spiral"] = spiral_bench(fp, w, dev)
+    print(f"# spiral: {rec['spiral']}", file=sys.stderr, flush=True)
     rec["schwarz_exchange"] = schwarz_bench(fp, w, dev, head)
     print(f"# schwarz exchange: {rec['schwarz_exchange']}", file=sys.stderr, flush=True)
     if args.serving_requests > 0:

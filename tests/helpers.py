@@ -1,6 +1,8 @@
 """Test-side closed forms: affine element maps of the box meshes and the
-analytic polynomial map of ``workloads.poly_map_mesh``."""
+analytic polynomial map of ``workloads.poly_map_mesh``, and exact points on
+the spiral element through a library interpolant."""
 import numpy as np
+import workloads as w
 
 
 def box_affine(ex, ey, ez, nxyz, lo, hi, r):
@@ -57,3 +59,21 @@ def box_surface(lo, hi, N=4):
                     ws.append(wq[i] * wq[j] * ja * jb)
                     ns.append(nn)
     return np.array(pts).T, np.array(ws), np.array(ns).T
+
+
+def spiral_exact_points(m, P, seed):
+    """P points x^e(r_true), r_true uniform in [-1, 1]^3, on element 0 of
+    mesh m, through scipy's barycentric Lagrange interpolation on the GLL
+    nodes: the tensor interpolant evaluated by a library routine, independent
+    of the oracle's basis and map.  Returns (points (P, 3), r_true (P, 3))."""
+    from scipy.interpolate import BarycentricInterpolator
+    N = m.N
+    rng = np.random.default_rng(seed)
+    rt = rng.uniform(-1, 1, (P, 3))
+    B = BarycentricInterpolator(w.gll_points(N), np.eye(N + 1))
+    L = [B(rt[:, d]) for d in range(3)]
+    hd = m.host()
+    pts = np.stack([np.einsum("pi,pj,pk,kji->p", L[0], L[1], L[2],
+                              hd[c][:(N + 1) ** 3].reshape(N + 1, N + 1, N + 1))
+                    for c in "xyz"], 1)
+    return pts, rt

@@ -239,6 +239,55 @@ def test_exact_recovery(dev):
     assert np.all(np.min(1 - np.abs(rt[~same]), axis=1) <= 1e-10)
 
 
+def test_spiral_n15(dev):
+    """The N = 15 spiral stand-in (Section 3.1): exact points x^e(r_true)
+    are all found with r_true recovered, points between the turns match the
+    oracle (both start Newton at the closest GLL node, so both settle in the
+    same local minimum), and evaluating the coordinate fields at the returned
+    (el, r) gives the points back.  At tol = 1e-14 the inside test sits at the
+    rounding floor of the binary64 map (|x| up to 4.6, h = 6.25), so the two
+    sides may call an exact point inside or border differently; there the
+    checks are r_true recovered, a distance at that floor, and every GPU
+    inside answer passing the oracle's residual to 1.5 tol h."""
+    fp = _fp()
+    from helpers import spiral_exact_points
+    _say("case: spiral element N=15, 1000 exact + 1000 box + 16 far points")
+    mesh = w.spiral_element()
+    om = oracle.OracleMesh.from_mesh(mesh, TOL)
+    b, hs = om.bbox()
+    ex, rt = spiral_exact_points(mesh, 1000, 19)
+    rng = np.random.default_rng(20)
+    box = rng.uniform(b[0, 0::2], b[0, 1::2], (1000, 3))
+    far = rng.uniform(-1, 1, (16, 3)) * 20.0 + 30.0
+    pts = np.concatenate([ex, box, far])
+    hd = mesh.host()
+    coords = [mesh.x, mesh.y, mesh.z]
+    h, g, out = _run(fp, mesh, torch.as_tensor(pts), dev, fields=coords)
+    gc, ge, gr, gd = g
+    st = compare_locate(om, pts, g, om.findpts(pts), hs, TOL)
+    assert np.all(gc[:1000] == 0) and np.all(ge[:1000] == 0)
+    assert np.max(np.abs(gr[:1000] - rt)) <= 1e-10
+    assert np.all(gc[2000:] == 2)
+    ins = gc == 0
+    back = out.T[ins]
+    assert np.max(np.abs(back - pts[ins])) <= 2 * TOL * hs[0]
+    ref = om.eval(g[0], g[1], g[2], [hd[c] for c in "xyz"])
+    compare_eval(out, ref, [hd[c] for c in "xyz"], rel=1e-13)
+    _say(f"spiral tol 1e-12: {st}")
+    tol = 1e-14
+    h14, g14, _ = _run(fp, mesh, torch.as_tensor(ex), dev, tol=tol)
+    om14 = oracle.OracleMesh.from_mesh(mesh, tol)
+    oc = om14.findpts(ex)[0]
+    gc, ge, gr, gd = g14
+    assert np.all(ge == 0) and np.all(gc <= 1)
+    assert np.max(np.abs(gr - rt)) <= 1e-11
+    assert np.sqrt(gd).max() <= 1e-13 * hs[0]
+    for i in np.nonzero(gc == 0)[0]:
+        x, _ = om14.map(0, gr[i])
+        assert np.linalg.norm(x - ex[i]) <= 1.5 * tol * hs[0], i
+    _say(f"spiral tol 1e-14: inside gpu {int(np.sum(gc == 0))} oracle {int(np.sum(oc == 0))} of 1000")
+
+
 def test_eval_reference_polynomials(dev):
     fp = _fp()
     _say("case: eval of reference-space polynomials, 3 fields, random (e, r)")

@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import workloads as w
-from helpers import box_affine, box_elem_ids, phi_np
+from helpers import box_affine, box_elem_ids, phi_np, spiral_exact_points
 
 
 def _residual(om, e, r, p):
@@ -126,3 +126,31 @@ def test_against_brute_force(case):
             assert d2[i] <= bd2[i] * (1 + 1e-10) + 1e-30, (i, d2[i], bd2[i])
         else:
             assert code[i] == 2
+
+
+
+def test_spiral_nearest_node_start():
+    """Section 3.1, spiral test: on one N = 15 element wound 1.5 times, Newton
+    started at the closest GLL node finds every point of the element, while a
+    start at the element's centre is trapped for a large share of them; for
+    points between the turns, no element point the brute-force multi-start
+    search finds is missed, and the returned distance never undercuts its
+    minimum (a returned local minimum may exceed it: the paper claims no
+    global minimum off the element)."""
+    m = w.spiral_element()
+    om = oracle.OracleMesh.from_mesh(m, 1e-12)
+    b, h = om.bbox()
+    pts, rt = spiral_exact_points(m, 1000, 17)
+    code, el, rst, d2 = om.findpts(pts)
+    assert np.all(code == 0) and np.all(el == 0)
+    assert np.max(np.abs(rst - rt)) <= 1e-10
+    assert np.sqrt(d2).max() <= 1e-12 * h[0]
+    trapped = sum(np.sqrt(om.newton(0, p, r0=np.zeros(3))[1]) > 1e-12 * h[0] for p in pts[:300])
+    assert trapped >= 30, trapped  # the centre start fails on this geometry
+    rng = np.random.default_rng(18)
+    q = rng.uniform(b[0, 0::2], b[0, 1::2], (300, 3))
+    code, el, rst, d2 = om.findpts(q)
+    bc, _, _, bd = om.brute(q, grid=4)
+    assert np.any(bc == 0) and np.any(bc == 1)
+    assert np.array_equal(code == 0, bc == 0)
+    assert np.all(d2 >= bd * (1 - 1e-10) - 1e-30)

@@ -22,6 +22,7 @@ from .meshes import (  # noqa: F401
     overlap_c3,
     big_box_c5,
     poly_map_mesh,
+    spiral_element,
     queries_uniform_box,
     queries_c1,
     queries_c2,

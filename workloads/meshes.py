@@ -177,6 +177,27 @@ def big_box_c5(device="cpu") -> Mesh:
     return _perturb(m, 0.02, 1.0, 2.0, 2.5)
 
 
+def spiral_element(N=15, turns=1.5, pitch=0.25, half=0.2, device="cpu") -> Mesh:
+    """One element of order N shaped as a thick spiral sheet, a stand-in for
+    the paper's N = 15 spiral (its geometry is not given).  Reference r runs
+    along the spiral, s across the sheet, t along z: the node at (r, s, t)
+    sits at angle th = turns * pi * (r + 1), radius 1 + pitch * th + half * s,
+    height t / 2.  Successive turns are 2 pi pitch apart (1.57 by default),
+    more than the sheet thickness 2 half (0.4), so the map is one-to-one,
+    while a point between the sheets sees a local minimum of the distance on
+    every turn it faces."""
+    z = torch.tensor(gll_points(N), dtype=torch.float64, device=device)
+    r = z[None, None, :].expand(N + 1, N + 1, N + 1)
+    s_ = z[None, :, None].expand(N + 1, N + 1, N + 1)
+    t = z[:, None, None].expand(N + 1, N + 1, N + 1)
+    th = turns * math.pi * (r + 1.0)
+    rad = 1.0 + pitch * th + half * s_
+    X = (rad * torch.cos(th))[None].contiguous()
+    Y = (rad * torch.sin(th))[None].contiguous()
+    Zc = (0.5 * t)[None].contiguous()
+    return Mesh("spiral", N, X, Y, Zc)
+
+
 def poly_map_mesh(nx, ny, nz, N, amp=0.04, device="cpu", name="polymap"):
     """Box mesh pushed through a fixed polynomial map Phi (exact in Q_N).
 
