@@ -146,40 +146,52 @@ hipEvent_t pool_event(fp_handle *h);
 // window j (positions [j K, (j + 1) K)) is unit s + j.  Along the list both s
 // and j never decrease and at least one of them grows from one piece to the
 // next, so the unit indices of the pieces are distinct and increasing, and
-// the segment holding unit u is the last s with s + b(s) / K <= u.  A block
-// takes units blockIdx.x, blockIdx.x + gridDim.x, ... below unit_end(): an
-// element with many points is spread over many blocks, an empty one costs a
-// search.  Units of gaps (empty segments, cuts that fall on a segment's
-// start) are empty.
+// the segment holding unit u is the last s with s + b(s) / K <= u, which lies
+// in [u - T, u] for T = b(ns) / K.  A block takes units blockIdx.x,
+// blockIdx.x + gridDim.x, ... below ns + T + 1: an element with many points
+// is spread over many blocks, and a sparse list (T small) needs no search.
+// Units of gaps (empty segments, cuts that fall on a segment's start) are
+// empty.
 struct Unit {
     int seg, beg, end;
 };
 
-__device__ __forceinline__ long long unit_end(const int *off, int ns, int ne, int K)
-{
-    return (long long)ns + off[ne] / K + 1;
-}
+struct UnitList {
+    const int *off;
+    int ns, gs, ne, K, T;
+    long long end;  // one past the last unit index
 
-__device__ __forceinline__ bool unit_at(long long u, const int *off, int ns, int gs, int ne,
-                                        int K, Unit &U)
-{
-    auto b = [&](long long s) { return off[s * gs < ne ? s * gs : ne]; };
-    int lo = 0, hi = ns - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (mid + b(mid) / K <= u)
-            lo = mid;
-        else
-            hi = mid - 1;
+    __host__ __device__ __forceinline__ UnitList(const int *off_, int ns_, int gs_, int ne_, int K_)
+        : off(off_), ns(ns_), gs(gs_), ne(ne_), K(K_)
+    {
+        T = off[ne] / K;
+        end = (long long)ns + T + 1;
     }
-    const int b0 = b(lo), b1 = b(lo + 1);
-    const long long j = u - lo;
-    if (b0 >= b1 || j * K >= b1) return false;
-    U.seg = lo;
-    U.beg = (int)(j * K > b0 ? j * K : b0);
-    U.end = (int)((j + 1) * K < b1 ? (j + 1) * K : b1);
-    return true;
-}
+    __host__ __device__ __forceinline__ int b(long long s) const
+    {
+        return off[s * gs < ne ? s * gs : ne];
+    }
+    __host__ __device__ __forceinline__ bool at(long long u, Unit &U) const
+    {
+        long long lo = u - T, hi = u;
+        if (lo < 0) lo = 0;
+        if (hi > ns - 1) hi = ns - 1;
+        while (lo < hi) {
+            const long long mid = (lo + hi + 1) >> 1;
+            if (mid + b(mid) / K <= u)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int b0 = b(lo), b1 = b(lo + 1);
+        const long long j = u - lo;
+        if (b0 >= b1 || j * K >= b1) return false;
+        U.seg = (int)lo;
+        U.beg = (int)(j * K > b0 ? j * K : b0);
+        U.end = (int)((j + 1) * K < b1 ? (j + 1) * K : b1);
+        return true;
+    }
+};
 
 // Blocks of a unit launch over ns segments for a list of at most about
 // 2 n entries.  Pieces beyond the grid are taken by the grid-stride walk.

@@ -377,10 +377,10 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
     constexpr int V = N1 * N1 * N1;
     const BasisPtr<double> B{as_const(basis)};
     unsigned long long my_iters = 0;
-    const long long nu = unit_end(a.elem_off, a.E, a.E, kUnitScalar);
-    for (long long u = blockIdx.x; u < nu; u += gridDim.x) {
+    const UnitList L(a.elem_off, a.E, 1, a.E, kUnitScalar);
+    for (long long u = blockIdx.x; u < L.end; u += gridDim.x) {
         Unit U;
-        if (!unit_at(u, a.elem_off, a.E, 1, a.E, kUnitScalar, U)) continue;
+        if (!L.at(u, U)) continue;
         const int e = U.seg;
         cptr<double> X = as_const(a.geom + (long long)e * 3 * V);
         const double he = a.esize[e];
