@@ -1,7 +1,8 @@
 /*
  * findpts_oracle.c -- plain, slow, double-precision CPU reference ("oracle")
  * for point location (findpts) and interpolation (findpts_eval) on meshes of
- * curved isoparametric hexahedral spectral elements.
+ * curved isoparametric hexahedral spectral elements, and (second part, or2_*)
+ * on meshes of curved quadrilateral elements in two dimensions.
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
  * CPU-baseline leg of the benchmark load this library.  It shares no code,
@@ -649,13 +650,13 @@ static double delta_at(const or_mesh *m, int e, const double *r)
  * ------------------------------------------------------------------------- */
 typedef struct { int e; double r[3], d2; int inside; double dl; int sess; } cand_t;
 
-static void select_point(const or_mesh *m, const cand_t *cs, int nc, int *code,
+static void select_cands(int has_delta, int dim, const cand_t *cs, int nc, int *code,
                          int *el, double *rst, double *dist2)
 {
     int w = -1, anyin = 0;
     for (int q = 0; q < nc; ++q) if (cs[q].inside) { anyin = 1; break; }
     if (anyin) {
-        if (m->delta) {
+        if (has_delta) {
             int bs = 0; double bd = -INFINITY; int have = 0;
             for (int q = 0; q < nc; ++q) {
                 if (!cs[q].inside) continue;
@@ -685,13 +686,19 @@ static void select_point(const or_mesh *m, const cand_t *cs, int nc, int *code,
     }
     if (w < 0) {
         *code = 2; *el = -1;
-        rst[0] = rst[1] = rst[2] = 0.0;
+        for (int d = 0; d < dim; ++d) rst[d] = 0.0;
         *dist2 = INFINITY;
         return;
     }
     *el = cs[w].e;
-    for (int d = 0; d < 3; ++d) rst[d] = cs[w].r[d];
+    for (int d = 0; d < dim; ++d) rst[d] = cs[w].r[d];
     *dist2 = cs[w].d2;
+}
+
+static void select_point(const or_mesh *m, const cand_t *cs, int nc, int *code,
+                         int *el, double *rst, double *dist2)
+{
+    select_cands(m->delta != NULL, 3, cs, nc, code, el, rst, dist2);
 }
 
 static void fill_cand(const or_mesh *m, cand_t *c, int e, const double *p,
@@ -807,6 +814,458 @@ void or_eval(const or_mesh *m, int npts, const int *code, const int *el,
             double v = NAN;
             if (code[p] != 2 && el[p] >= 0 && el[p] < m->E)
                 v = interp(m, fields[f] + (size_t)el[p] * m->V, rst + 3 * (size_t)p);
+            out[(size_t)f * npts + p] = v;
+        }
+    }
+}
+
+/* ===========================================================================
+ * Two dimensions: meshes of curved quadrilateral spectral elements.
+ *
+ * The paper's method and its 2D figures (Figs. 1 and 6) carry over with the
+ * reference square [-1,1]^2: x_c(r, s) = sum_ij X_c[i + n1 j] h_i(r) h_j(s)
+ * for c = x, y; boxes, hash, closest-node start, trust-region Newton,
+ * classification, selection and interpolation follow the 3D readings above
+ * with two coordinates (hash: about E cells, n_a = round(ext_a (E/area)^(1/2))).
+ * Everything below is written out again for two dimensions; only the 1D
+ * helpers (GLL, Lagrange, Bernstein inverse, small solve) and the selection
+ * rule are shared with the 3D code.
+ * ========================================================================= */
+typedef struct {
+    int E, N, n1, V;
+    double tol;
+    const double *X[2];    /* borrowed: x, y, each E*V, r index fastest */
+    const int *esess;
+    const double *delta;
+    double z[OR_MAXN1], w[OR_MAXN1];
+    double *bbox;          /* E*4: xmin xmax ymin ymax */
+    double *h;
+    double lo[2], hi[2], dx[2];
+    int nc[2];
+    int *cell_off, *cell_el;
+} or2_mesh;
+
+static inline const double *elem2(const or2_mesh *m, int c, int e)
+{
+    return m->X[c] + (size_t)e * m->V;
+}
+
+static void emap2(const or2_mesh *m, int e, const double r[2], double x[2], double J[4])
+{
+    int n1 = m->n1;
+    double hr[OR_MAXN1], hs[OR_MAXN1], dr[OR_MAXN1], ds[OR_MAXN1];
+    lagrange(m->N, m->z, r[0], hr, dr);
+    lagrange(m->N, m->z, r[1], hs, ds);
+    for (int c = 0; c < 2; ++c) {
+        const double *Xc = elem2(m, c, e);
+        double v = 0, vr = 0, vs = 0;
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n1; ++i) {
+                double X = Xc[i + n1 * j];
+                v  += X * hr[i] * hs[j];
+                vr += X * dr[i] * hs[j];
+                vs += X * hr[i] * ds[j];
+            }
+        x[c] = v;
+        if (J) { J[2 * c] = vr; J[2 * c + 1] = vs; }
+    }
+}
+
+static double interp2(const or2_mesh *m, const double *F, const double r[2])
+{
+    int n1 = m->n1;
+    double hr[OR_MAXN1], hs[OR_MAXN1];
+    lagrange(m->N, m->z, r[0], hr, NULL);
+    lagrange(m->N, m->z, r[1], hs, NULL);
+    double f = 0.0;
+    for (int j = 0; j < n1; ++j) {
+        double fr = 0.0;
+        for (int i = 0; i < n1; ++i) fr += hr[i] * F[i + n1 * j];
+        f += hs[j] * fr;
+    }
+    return f;
+}
+
+static void element_bbox2(const or2_mesh *m, const double *Binv, int e)
+{
+    int n1 = m->n1, V = m->V;
+    double *a = malloc(sizeof(double) * V), *b = malloc(sizeof(double) * V);
+    double he = 0.0, xmax = 0.0, lo[2], hi[2];
+    for (int c = 0; c < 2; ++c) {
+        const double *Xc = elem2(m, c, e);
+        double mn = Xc[0], mx = Xc[0];
+        for (int q = 0; q < V; ++q) {
+            if (Xc[q] < mn) mn = Xc[q];
+            if (Xc[q] > mx) mx = Xc[q];
+            if (fabs(Xc[q]) > xmax) xmax = fabs(Xc[q]);
+        }
+        if (mx - mn > he) he = mx - mn;
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n1; ++i) {
+                double t = 0.0;
+                for (int l = 0; l < n1; ++l) t += Binv[i * n1 + l] * Xc[l + n1 * j];
+                a[i + n1 * j] = t;
+            }
+        for (int j = 0; j < n1; ++j)
+            for (int i = 0; i < n1; ++i) {
+                double t = 0.0;
+                for (int l = 0; l < n1; ++l) t += Binv[j * n1 + l] * a[i + n1 * l];
+                b[i + n1 * j] = t;
+            }
+        lo[c] = b[0]; hi[c] = b[0];
+        for (int q = 0; q < V; ++q) {
+            if (b[q] < lo[c]) lo[c] = b[q];
+            if (b[q] > hi[c]) hi[c] = b[q];
+        }
+    }
+    double marg = 1e-8 * he + 1e-14 * xmax;
+    for (int c = 0; c < 2; ++c) {
+        m->bbox[4 * e + 2 * c] = lo[c] - marg;
+        m->bbox[4 * e + 2 * c + 1] = hi[c] + marg;
+    }
+    m->h[e] = he;
+    free(a); free(b);
+}
+
+static int cell_of2(const or2_mesh *m, int a, double x)
+{
+    double u = (x - m->lo[a]) / m->dx[a];
+    int i = (int)floor(u);
+    if (i < 0) i = 0;
+    if (i > m->nc[a] - 1) i = m->nc[a] - 1;
+    return i;
+}
+
+static void build_hash2(or2_mesh *m)
+{
+    int E = m->E;
+    for (int a = 0; a < 2; ++a) { m->lo[a] = m->bbox[2 * a]; m->hi[a] = m->bbox[2 * a + 1]; }
+    for (int e = 1; e < E; ++e)
+        for (int a = 0; a < 2; ++a) {
+            if (m->bbox[4 * e + 2 * a] < m->lo[a]) m->lo[a] = m->bbox[4 * e + 2 * a];
+            if (m->bbox[4 * e + 2 * a + 1] > m->hi[a]) m->hi[a] = m->bbox[4 * e + 2 * a + 1];
+        }
+    double ext[2], area = 1.0;
+    for (int a = 0; a < 2; ++a) {
+        ext[a] = m->hi[a] - m->lo[a];
+        if (!(ext[a] > 0.0)) ext[a] = 1e-300;
+        area *= ext[a];
+    }
+    double dens = sqrt((double)E / area);
+    for (int a = 0; a < 2; ++a) {
+        double n = floor(ext[a] * dens + 0.5);
+        if (n < 1.0) n = 1.0;
+        if (n > 65536.0) n = 65536.0;
+        m->nc[a] = (int)n;
+        m->dx[a] = ext[a] / m->nc[a];
+    }
+    long ncell = (long)m->nc[0] * m->nc[1];
+    int *cnt = calloc(ncell + 1, sizeof(int));
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) {
+            m->cell_off = malloc(sizeof(int) * (ncell + 1));
+            m->cell_off[0] = 0;
+            for (long c = 0; c < ncell; ++c) m->cell_off[c + 1] = m->cell_off[c] + cnt[c];
+            m->cell_el = malloc(sizeof(int) * (m->cell_off[ncell] + 1));
+            memset(cnt, 0, sizeof(int) * ncell);
+        }
+        for (int e = 0; e < E; ++e) {
+            const double *b = m->bbox + 4 * e;
+            int i0 = cell_of2(m, 0, b[0]), i1 = cell_of2(m, 0, b[1]);
+            int j0 = cell_of2(m, 1, b[2]), j1 = cell_of2(m, 1, b[3]);
+            for (int j = j0; j <= j1; ++j)
+                for (int i = i0; i <= i1; ++i) {
+                    long c = i + (long)m->nc[0] * j;
+                    if (pass == 1) m->cell_el[m->cell_off[c] + cnt[c]] = e;
+                    cnt[c]++;
+                }
+        }
+    }
+    free(cnt);
+}
+
+or2_mesh *or2_setup(int E, int N, const double *x, const double *y, double tol,
+                    const int *esess, const double *delta)
+{
+    if (E < 1 || N < 1 || N > OR_MAXN1 - 1) return NULL;
+    or2_mesh *m = calloc(1, sizeof(or2_mesh));
+    m->E = E; m->N = N; m->n1 = N + 1; m->V = m->n1 * m->n1;
+    m->tol = tol;
+    m->X[0] = x; m->X[1] = y;
+    m->esess = esess; m->delta = delta;
+    or_gll(N, m->z, m->w);
+    m->bbox = malloc(sizeof(double) * 4 * E);
+    m->h = malloc(sizeof(double) * E);
+    double Binv[OR_MAXN1 * OR_MAXN1];
+    bernstein_inverse(N, m->z, Binv);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int e = 0; e < E; ++e) element_bbox2(m, Binv, e);
+    build_hash2(m);
+    return m;
+}
+
+void or2_free(or2_mesh *m)
+{
+    if (!m) return;
+    free(m->bbox); free(m->h); free(m->cell_off); free(m->cell_el); free(m);
+}
+
+void or2_get_bbox(const or2_mesh *m, double *bbox, double *h)
+{
+    memcpy(bbox, m->bbox, sizeof(double) * 4 * m->E);
+    memcpy(h, m->h, sizeof(double) * m->E);
+}
+
+void or2_map(const or2_mesh *m, int e, const double *r, double *x, double *J)
+{
+    emap2(m, e, r, x, J);
+}
+
+static int in_box2(const double *b, const double *p)
+{
+    return p[0] >= b[0] && p[0] <= b[1] && p[1] >= b[2] && p[1] <= b[3];
+}
+
+int or2_candidates(const or2_mesh *m, const double *p, int psess, int *out, int max)
+{
+    for (int a = 0; a < 2; ++a)
+        if (!(p[a] >= m->lo[a] && p[a] <= m->hi[a])) return 0;
+    long c = cell_of2(m, 0, p[0]) + (long)m->nc[0] * cell_of2(m, 1, p[1]);
+    int n = 0;
+    for (int q = m->cell_off[c]; q < m->cell_off[c + 1]; ++q) {
+        int e = m->cell_el[q];
+        if (!in_box2(m->bbox + 4 * e, p)) continue;
+        if (psess >= 0 && m->esess && m->esess[e] == psess) continue;
+        if (n < max) out[n] = e;
+        n++;
+    }
+    return n;
+}
+
+static void start_node2(const or2_mesh *m, int e, const double *p, double r[2])
+{
+    int n1 = m->n1, best = 0;
+    double bd = INFINITY;
+    for (int q = 0; q < m->V; ++q) {
+        double d = 0.0;
+        for (int c = 0; c < 2; ++c) {
+            double t = elem2(m, c, e)[q] - p[c];
+            d += t * t;
+        }
+        if (d < bd) { bd = d; best = q; }
+    }
+    r[0] = m->z[best % n1];
+    r[1] = m->z[best / n1];
+}
+
+static double resid2(const or2_mesh *m, int e, const double *p, const double r[2],
+                     double F[2], double J[4])
+{
+    double x[2];
+    emap2(m, e, r, x, J);
+    double phi = 0.0;
+    for (int c = 0; c < 2; ++c) { F[c] = x[c] - p[c]; phi += F[c] * F[c]; }
+    return phi;
+}
+
+/* The 3D trust-region rules (constants, active set, radius updates, stops)
+ * on [-1,1]^2. */
+static int tr_newton2(const or2_mesh *m, int e, const double *p, double r[2],
+                      double *phi_out)
+{
+    double he = m->h[e];
+    double F[2], J[4], D = 1.0;
+    double phi = resid2(m, e, p, r, F, J);
+    int it = 0;
+    while (it < OR_MAXIT) {
+        if (phi <= (1e-13 * he) * (1e-13 * he)) break;
+        ++it;
+        double g[2];
+        for (int d = 0; d < 2; ++d) g[d] = J[d] * F[0] + J[2 + d] * F[1];
+        int fr[2], nf = 0;
+        for (int d = 0; d < 2; ++d) {
+            int held = (r[d] >= 1.0 && g[d] < 0.0) || (r[d] <= -1.0 && g[d] > 0.0);
+            if (!held) fr[nf++] = d;
+        }
+        if (nf == 0) break;
+        double dl[2] = {0.0, 0.0};
+        int bad;
+        if (nf == 2) {
+            double A[3][3], b[3];
+            for (int i = 0; i < 2; ++i) {
+                for (int j = 0; j < 2; ++j) A[i][j] = J[2 * i + j];
+                b[i] = -F[i];
+            }
+            bad = solve_small(2, A, b, dl);
+        } else {
+            int da = fr[0];
+            double a = J[da] * J[da] + J[2 + da] * J[2 + da];
+            bad = !(a != 0.0);
+            if (!bad) {
+                dl[da] = -g[da] / a;
+                if (!isfinite(dl[da])) bad = 1;
+            }
+        }
+        if (bad) {
+            dl[0] = dl[1] = 0.0;
+            for (int a = 0; a < nf; ++a) dl[fr[a]] = -g[fr[a]];
+        }
+        double nd = fabs(dl[0]) > fabs(dl[1]) ? fabs(dl[0]) : fabs(dl[1]);
+        if (!(nd > 0.0) || !isfinite(nd)) break;
+        int limited = 0;
+        if (nd > D) {
+            double sc = D / nd;
+            dl[0] *= sc; dl[1] *= sc;
+            limited = 1;
+        }
+        double rn[2], s[2], ns = 0.0;
+        for (int d = 0; d < 2; ++d) {
+            double v = r[d] + dl[d];
+            if (v > 1.0) v = 1.0;
+            if (v < -1.0) v = -1.0;
+            rn[d] = v;
+            s[d] = v - r[d];
+            if (fabs(s[d]) > ns) ns = fabs(s[d]);
+        }
+        if (ns <= 1e-15) break;
+        double pred = phi;
+        for (int c = 0; c < 2; ++c) {
+            double t = F[c] + J[2 * c] * s[0] + J[2 * c + 1] * s[1];
+            pred -= t * t;
+        }
+        if (!(pred > 0.0)) break;
+        double Fn[2], Jn[4];
+        double phin = resid2(m, e, p, rn, Fn, Jn);
+        double rho = (phi - phin) / pred;
+        int acc = rho >= 0.01;
+        if (acc) {
+            for (int d = 0; d < 2; ++d) { r[d] = rn[d]; F[d] = Fn[d]; }
+            for (int q = 0; q < 4; ++q) J[q] = Jn[q];
+            phi = phin;
+        }
+        if (rho > 0.75 && limited) { D = 2.0 * D; if (D > 2.0) D = 2.0; }
+        else if (rho < 0.25) D = 0.25 * ns;
+        if (acc && ns <= 1e-13) break;
+    }
+    *phi_out = phi;
+    return it;
+}
+
+int or2_newton(const or2_mesh *m, int e, const double *p, double *r, double *d2)
+{
+    start_node2(m, e, p, r);
+    return tr_newton2(m, e, p, r, d2);
+}
+
+int or2_newton_from(const or2_mesh *m, int e, const double *p, double *r, double *d2)
+{
+    return tr_newton2(m, e, p, r, d2);
+}
+
+static void fill_cand2(const or2_mesh *m, cand_t *c, int e, const double *p, const double *r)
+{
+    c->e = e;
+    c->r[0] = r[0]; c->r[1] = r[1]; c->r[2] = 0.0;
+    double F[2];
+    c->d2 = resid2(m, e, p, c->r, F, NULL);
+    c->inside = sqrt(c->d2) <= m->tol * m->h[e];
+    c->sess = m->esess ? m->esess[e] : 0;
+    c->dl = (m->delta && c->inside) ? interp2(m, m->delta + (size_t)e * m->V, c->r) : 0.0;
+}
+
+/* findpts in 2D: pts (x, y interleaved), rst receives (r, s) per point. */
+void or2_findpts(const or2_mesh *m, int npts, const double *pts, const int *psess,
+                 int *code, int *el, double *rst, double *dist2, long long *stats,
+                 int nthreads)
+{
+    long long tc = 0, ti = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel reduction(+ : tc, ti)
+    {
+        int *ids = malloc(sizeof(int) * m->E);
+        cand_t *cs = malloc(sizeof(cand_t) * m->E);
+#pragma omp for schedule(dynamic, 1024)
+        for (int p = 0; p < npts; ++p) {
+            const double *x = pts + 2 * (size_t)p;
+            int nc = or2_candidates(m, x, psess ? psess[p] : -1, ids, m->E);
+            for (int q = 0; q < nc; ++q) {
+                double r[2], d2;
+                ti += or2_newton(m, ids[q], x, r, &d2);
+                fill_cand2(m, &cs[q], ids[q], x, r);
+            }
+            tc += nc;
+            select_cands(m->delta != NULL, 2, cs, nc, code + p, el + p, rst + 2 * (size_t)p,
+                         dist2 + p);
+        }
+        free(ids); free(cs);
+    }
+    if (stats) { stats[0] = tc; stats[1] = ti; }
+}
+
+/* Brute force in 2D: all elements (or those whose box holds the point),
+ * starts at the closest node, every node (all_nodes) and a g x g grid. */
+void or2_brute(const or2_mesh *m, int npts, const double *pts, const int *psess,
+               int g, int all_nodes, int only_boxes, int *code, int *el,
+               double *rst, double *dist2, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        cand_t *cs = malloc(sizeof(cand_t) * m->E);
+#pragma omp for schedule(dynamic, 1)
+        for (int p = 0; p < npts; ++p) {
+            const double *x = pts + 2 * (size_t)p;
+            int nc = 0;
+            for (int e = 0; e < m->E; ++e) {
+                if (psess && psess[p] >= 0 && m->esess && m->esess[e] == psess[p]) continue;
+                if (only_boxes && !in_box2(m->bbox + 4 * e, x)) continue;
+                double br[2], bd, r[2], d2;
+                or2_newton(m, e, x, r, &d2);
+                bd = d2; br[0] = r[0]; br[1] = r[1];
+                int nn = all_nodes ? m->V : 0;
+                for (int q = 0; q < nn + g * g; ++q) {
+                    if (q < nn) {
+                        r[0] = m->z[q % m->n1]; r[1] = m->z[q / m->n1];
+                    } else {
+                        int u = q - nn;
+                        r[0] = -1.0 + 2.0 * (u % g) / (g - 1);
+                        r[1] = -1.0 + 2.0 * (u / g) / (g - 1);
+                    }
+                    tr_newton2(m, e, x, r, &d2);
+                    if (d2 < bd) { bd = d2; br[0] = r[0]; br[1] = r[1]; }
+                }
+                fill_cand2(m, &cs[nc], e, x, br);
+                nc++;
+            }
+            select_cands(m->delta != NULL, 2, cs, nc, code + p, el + p, rst + 2 * (size_t)p,
+                         dist2 + p);
+        }
+        free(cs);
+    }
+}
+
+void or2_eval(const or2_mesh *m, int npts, const int *code, const int *el, const double *rs,
+              int nf, const double *const *fields, double *out, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int p = 0; p < npts; ++p) {
+        for (int f = 0; f < nf; ++f) {
+            double v = NAN;
+            if (code[p] != 2 && el[p] >= 0 && el[p] < m->E)
+                v = interp2(m, fields[f] + (size_t)el[p] * m->V, rs + 2 * (size_t)p);
             out[(size_t)f * npts + p] = v;
         }
     }

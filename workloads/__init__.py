@@ -40,3 +40,13 @@ from .serving import (  # noqa: F401
     serving_requests,
     serving_points,
 )
+from .meshes2d import (  # noqa: F401
+    Mesh2,
+    box2d_mesh,
+    annulus2d_mesh,
+    poly_map_mesh2d,
+    phi2,
+    overlap2d,
+    annulus2d_c6,
+    queries2d_c6,
+)
