@@ -196,6 +196,55 @@ FP_API int findpts_footprint(const fp_handle *h, size_t *h_bytes);
  * synchronisation).  NULL is a no-op. */
 FP_API int findpts_free(fp_handle *h);
 
+/*
+ * Two dimensions: meshes of curved quadrilateral spectral elements of order
+ * N (the method of Section 2.1 on the reference square [-1,1]^2; the
+ * paper's Figs. 1 and 6 are two-dimensional overlapping meshes).  Node (i, j)
+ * of element e is at flat index i + (N+1) (j + (N+1) e).  Readings as in three
+ * dimensions: Bernstein-hull boxes with the same margin, h_e = largest
+ * per-axis node extent, closest-node start (smallest index on ties), the same
+ * trust-region rules on [-1,1]^2, the same classification and selection.
+ *
+ * findpts2_setup -- like findpts_setup: x, y hold E*(N+1)^2 doubles each,
+ * elem_session E ints or NULL, delta E*(N+1)^2 doubles or NULL; all device
+ * pointers, copied.  Synchronises `stream`.  Errors: FP_EINVAL, FP_ERANGE,
+ * FP_ENOMEM, FP_EHIP.
+ */
+typedef struct fp2_handle fp2_handle; /* opaque, owned by the library */
+FP_API int findpts2_setup(fp2_handle **h, const double *x, const double *y, int E, int N,
+                          double tol, const int *elem_session, const double *delta,
+                          int max_points, void *stream);
+
+/*
+ * findpts2 -- locate npts points: pts npts*2 doubles (x y interleaved),
+ * pt_session npts ints or NULL, out code / el (npts ints), rs (npts*2
+ * doubles: r, s), dist2 (npts doubles), as for findpts.  Allocates nothing;
+ * calls on one handle must not overlap (they share its workspace).
+ */
+FP_API int findpts2(fp2_handle *h, int npts, const double *pts, const int *pt_session,
+                    int *code, int *el, double *rs, double *dist2, void *stream);
+
+/*
+ * findpts2_eval -- f(e, r, s) = sum_ij F^e_ij h_i(r) h_j(s) for nfields
+ * fields (host array of device pointers, each E*(N+1)^2 doubles) at located
+ * points; out nfields*npts doubles, field-major; FP_NOT_FOUND gives NaN.
+ * Allocates nothing; shares the handle's workspace with findpts2.
+ */
+FP_API int findpts2_eval(fp2_handle *h, int npts, const int *code, const int *el,
+                         const double *rs, int nfields, const double *const *h_fields,
+                         double *out, void *stream);
+
+/* Pairs solved and Newton iterations since setup (h_counts: 2 host long
+ * longs); reset != 0 zeroes them.  Synchronous. */
+FP_API int findpts2_stats(fp2_handle *h, long long *h_counts, int reset);
+
+/* Element boxes (host E*4 doubles: xmin xmax ymin ymax) and sizes h_e (host E
+ * doubles).  Synchronous. */
+FP_API int findpts2_get_bbox(fp2_handle *h, double *h_bbox, double *h_size);
+
+/* Release a handle (NULL is a no-op); waits for the device first. */
+FP_API int findpts2_free(fp2_handle *h);
+
 /* Message of the last error on the calling thread ("" if none). */
 FP_API const char *fp_last_error(void);
 

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfindpts.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["fp_util.hip", "fp_setup.hip", "fp_locate.hip", "fp_eval.hip", "fp_serve.hip",
-           "fp_interface.hip"]
+           "fp_interface.hip", "fp_2d.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",

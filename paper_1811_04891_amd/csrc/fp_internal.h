@@ -208,6 +208,11 @@ int scan_tmp_size(long long n);
 hipError_t scan_exclusive(const int *in, int *out, int n, int *tmp,
                           hipStream_t s);
 
+// GLL nodes and barycentric weights of order N; the inverse of the
+// Bernstein-to-nodal matrix (n1 x n1, row-major), both computed on the host.
+Basis make_basis(int N);
+std::vector<double> bernstein_to_nodal_inverse(int N, const double *z);
+
 // Fill n ints with a value (a kernel, so that it may be graph-captured).
 hipError_t fill_int(int *p, int value, long long n, hipStream_t s);
 

@@ -59,7 +59,7 @@ static void gll_nodes(int N, double *z)
     if (N % 2 == 0) z[N / 2] = 0.0;
 }
 
-static Basis make_basis(int N)
+Basis make_basis(int N)
 {
     Basis b{};
     gll_nodes(N, b.z);
@@ -75,7 +75,7 @@ static Basis make_basis(int N)
 // Inverse of M[i][k] = C(N,k) u_i^k (1-u_i)^(N-k), u_i = (1 + z_i)/2: maps
 // nodal values to tensor-Bernstein coefficients.  Gauss-Jordan in long
 // double on the host.
-static std::vector<double> bernstein_to_nodal_inverse(int N, const double *z)
+std::vector<double> bernstein_to_nodal_inverse(int N, const double *z)
 {
     const int n = N + 1;
     std::vector<long double> A(n * 2 * n, 0.0L);

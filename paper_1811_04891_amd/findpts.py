@@ -29,7 +29,9 @@ SYMBOLS = ("findpts_setup", "findpts_update", "findpts", "findpts_eval", "findpt
            "findpts_footprint", "findpts_free", "fp_last_error", "fp_copy",
            "fp_flux_correct", "fp_extrapolate",
            "fps_create", "fps_add_mesh", "fps_submit", "fps_wait", "fps_latency",
-           "fps_destroy")
+           "fps_destroy",
+           "findpts2_setup", "findpts2", "findpts2_eval", "findpts2_stats",
+           "findpts2_get_bbox", "findpts2_free")
 
 FP_FLUX_WORK = 1024
 
@@ -78,6 +80,13 @@ def lib():
     L.fps_wait.argtypes = [vp, C.c_longlong, C.c_double]
     L.fps_latency.argtypes = [vp, dp, dp, dp, llp, C.c_int]
     L.fps_destroy.argtypes = [vp]
+    L.findpts2_setup.argtypes = [C.POINTER(vp), vp, vp, C.c_int, C.c_int, C.c_double, vp, vp,
+                                 C.c_int, vp]
+    L.findpts2.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp]
+    L.findpts2_eval.argtypes = [vp, C.c_int, vp, vp, vp, C.c_int, C.POINTER(vp), vp, vp]
+    L.findpts2_stats.argtypes = [vp, llp, C.c_int]
+    L.findpts2_get_bbox.argtypes = [vp, dp, dp]
+    L.findpts2_free.argtypes = [vp]
     for name in SYMBOLS:
         if name != "fp_last_error":
             getattr(L, name).restype = C.c_int
@@ -385,3 +394,96 @@ class Server:
             self.destroy()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Two dimensions (quadrilateral elements): findpts2_*.
+# ---------------------------------------------------------------------------
+class Handle2:
+    """Owns an fp2_handle*; freed with findpts2_free."""
+
+    def __init__(self, ptr: C.c_void_p, E: int, N: int, device: torch.device):
+        self.ptr, self.E, self.N, self.device = ptr, E, N, device
+        self.n1 = N + 1
+        self.V = self.n1 ** 2
+
+    def free(self):
+        if self.ptr is not None and self.ptr.value:
+            _check(lib().findpts2_free(self.ptr), "findpts2_free")
+        self.ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def findpts2_setup(x: torch.Tensor, y: torch.Tensor, N: int, tol: float = 1e-12,
+                   elem_session: Optional[torch.Tensor] = None,
+                   delta: Optional[torch.Tensor] = None, max_points: int = 1 << 20,
+                   stream=None) -> Handle2:
+    V = (N + 1) ** 2
+    if x.numel() % V:
+        raise ValueError("coordinate arrays must hold E*(N+1)^2 values")
+    E = x.numel() // V
+    h = C.c_void_p()
+    rc = lib().findpts2_setup(C.byref(h), _ptr(x, torch.float64, "x", E * V),
+                              _ptr(y, torch.float64, "y", E * V), E, N, float(tol),
+                              _ptr(elem_session, torch.int32, "elem_session", E),
+                              _ptr(delta, torch.float64, "delta", E * V), int(max_points),
+                              _stream(stream))
+    _check(rc, "findpts2_setup")
+    return Handle2(h, E, N, x.device)
+
+
+def findpts2(h: Handle2, pts: torch.Tensor, pt_session: Optional[torch.Tensor] = None,
+             code=None, el=None, rs=None, dist2=None, stream=None):
+    """Locate pts (npts x 2, float64).  Returns (code, el, rs, dist2)."""
+    n = pts.numel() // 2
+    dev = pts.device
+    code = torch.empty(n, dtype=torch.int32, device=dev) if code is None else code
+    el = torch.empty(n, dtype=torch.int32, device=dev) if el is None else el
+    rs = torch.empty((n, 2), dtype=torch.float64, device=dev) if rs is None else rs
+    dist2 = torch.empty(n, dtype=torch.float64, device=dev) if dist2 is None else dist2
+    rc = lib().findpts2(h.ptr, n, _ptr(pts, torch.float64, "pts", 2 * n),
+                        _ptr(pt_session, torch.int32, "pt_session", n),
+                        _ptr(code, torch.int32, "code", n), _ptr(el, torch.int32, "el", n),
+                        _ptr(rs, torch.float64, "rs", 2 * n),
+                        _ptr(dist2, torch.float64, "dist2", n), _stream(stream))
+    _check(rc, "findpts2")
+    return code, el, rs, dist2
+
+
+def findpts2_eval(h: Handle2, code: torch.Tensor, el: torch.Tensor, rs: torch.Tensor,
+                  fields: Sequence[torch.Tensor], out: Optional[torch.Tensor] = None,
+                  stream=None) -> torch.Tensor:
+    """Interpolate fields (each E*(N+1)^2 float64) at located points.
+    Returns out (nfields x npts)."""
+    n = code.numel()
+    nf = len(fields)
+    if out is None:
+        out = torch.empty((nf, n), dtype=torch.float64, device=code.device)
+    arr = (C.c_void_p * max(nf, 1))(*[_ptr(f, torch.float64, f"fields[{i}]", h.E * h.V)
+                                       for i, f in enumerate(fields)])
+    rc = lib().findpts2_eval(h.ptr, n, _ptr(code, torch.int32, "code", n),
+                             _ptr(el, torch.int32, "el", n),
+                             _ptr(rs, torch.float64, "rs", 2 * n), nf, arr,
+                             _ptr(out, torch.float64, "out", nf * n), _stream(stream))
+    _check(rc, "findpts2_eval")
+    return out
+
+
+def findpts2_stats(h: Handle2, reset: bool = False):
+    """(pairs solved, Newton iterations) since setup/reset."""
+    v = (C.c_longlong * 2)()
+    _check(lib().findpts2_stats(h.ptr, v, int(bool(reset))), "findpts2_stats")
+    return tuple(v)
+
+
+def findpts2_get_bbox(h: Handle2):
+    import numpy as np
+    b, s = np.zeros(4 * h.E), np.zeros(h.E)
+    _check(lib().findpts2_get_bbox(h.ptr, b.ctypes.data_as(C.POINTER(C.c_double)),
+                                   s.ctypes.data_as(C.POINTER(C.c_double))), "findpts2_get_bbox")
+    return b.reshape(h.E, 4), s

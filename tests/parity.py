@@ -23,7 +23,7 @@ FACE_TOL = 1e-10
 def compare_locate(om, pts, gpu, ora, h, tol, max_report=5, check_residual_every=1):
     gc, ge, gr, gd = gpu
     oc, oe, orr, od = ora
-    pts = np.asarray(pts).reshape(-1, 3)
+    pts = np.asarray(pts).reshape(len(gc), -1)  # 3D (x y z) or 2D (x y) points
     bad = []
     n = len(gc)
     # not found

@@ -85,3 +85,20 @@ def test_serving_argument_checks_without_gpu():
     d = C.c_double()
     assert L.fps_latency(None, C.byref(d), C.byref(d), C.byref(d), None, 0) == fp.FP_EINVAL
     assert L.fps_destroy(None) == fp.FP_OK
+
+
+def test_2d_argument_checks_without_gpu():
+    L = fp.lib()
+    h = C.c_void_p()
+    x = C.c_void_p(16)  # never dereferenced: checks fail first
+    assert L.findpts2_setup(None, x, x, 1, 3, 1e-12, None, None, 10, None) == fp.FP_EINVAL
+    assert L.findpts2_setup(C.byref(h), None, x, 1, 3, 1e-12, None, None, 10, None) == fp.FP_EINVAL
+    assert L.findpts2_setup(C.byref(h), x, x, 1, 0, 1e-12, None, None, 10, None) == fp.FP_ERANGE
+    assert L.findpts2_setup(C.byref(h), x, x, 1, 16, 1e-12, None, None, 10, None) == fp.FP_ERANGE
+    assert L.findpts2_setup(C.byref(h), x, x, 0, 3, 1e-12, None, None, 10, None) == fp.FP_EINVAL
+    assert L.findpts2_setup(C.byref(h), x, x, 1, 3, 1.0, None, None, 10, None) == fp.FP_EINVAL
+    assert L.findpts2_setup(C.byref(h), x, x, 1, 3, 1e-12, None, None, 0, None) == fp.FP_EINVAL
+    assert L.findpts2(None, 1, None, None, None, None, None, None, None) == fp.FP_EINVAL
+    assert L.findpts2_eval(None, 1, None, None, None, 1, None, None, None) == fp.FP_EINVAL
+    assert L.findpts2_free(None) == fp.FP_OK
+    assert L.fp_last_error().decode() != ""
