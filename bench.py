@@ -16,6 +16,7 @@ Prints one JSON line.  Besides the throughput it reports:
   cpu_baseline  the CPU oracle timed on a bounded sample of the same points
   spiral        the N = 15 spiral element at tol 1e-14: 1000 points (the
                 paper's robustness case) and 1e6 points
+  twod          the two-dimensional path on a 16,384-element ring
   serving       a stream of requests on 16 resident meshes through the
                 serving layer: saturated throughput and p50/p99 latency at
                 0.5, 0.8 and 0.95 of the saturated request rate
@@ -299,6 +300,75 @@ def spiral_bench(fp, w, dev, reps=20):
     return out
 
 
+def locate2_flops_per_pair(N, K):
+    """Algorithmic binary64 flops of one 2D pair: closest-node scan (5 per
+    node) and K + 1 evaluations of the map and Jacobian (two coordinates:
+    4 V for the r contraction of value and derivative, 6 n1 for the s
+    contractions, plus 20 n1 for the basis and its derivative in r and s)."""
+    n1 = N + 1
+    V = n1 * n1
+    return 5 * V + (K + 1) * (8 * V + 32 * n1)
+
+
+def twod_bench(fp, w, dev, steps=20, warmup=3, nfields=4):
+    """Two-dimensional path on the 16,384-element ring (N = 7, 1.01e6 points,
+    4 fields): findpts2 + findpts2_eval per step."""
+    import numpy as np
+    import torch
+    m = w.annulus2d_c6(device=dev)
+    pts = w.queries2d_c6(device=dev)
+    P = pts.shape[0]
+    g = torch.Generator(device="cpu").manual_seed(8)
+    fl = [torch.randn((m.E, m.N + 1, m.N + 1), generator=g, dtype=torch.float64).to(dev)
+          for _ in range(nfields)]
+    t0 = time.perf_counter()
+    h = fp.findpts2_setup(m.x, m.y, m.N, tol=1e-12, max_points=1 << 20)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    code = torch.empty(P, dtype=torch.int32, device=dev)
+    el = torch.empty(P, dtype=torch.int32, device=dev)
+    rs = torch.empty((P, 2), dtype=torch.float64, device=dev)
+    d2 = torch.empty(P, dtype=torch.float64, device=dev)
+    out = torch.empty((nfields, P), dtype=torch.float64, device=dev)
+
+    def locate():
+        fp.findpts2(h, pts, None, code, el, rs, d2)
+
+    def step():
+        locate()
+        fp.findpts2_eval(h, code, el, rs, fl, out)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    fp.findpts2_stats(h, reset=True)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        step()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    pairs, iters = fp.findpts2_stats(h)
+    a.record()
+    for _ in range(steps):
+        locate()
+    b.record()
+    torch.cuda.synchronize()
+    ms_loc = a.elapsed_time(b) / steps
+    K = iters / max(pairs, 1)
+    flops = locate2_flops_per_pair(m.N, K) * pairs / steps
+    codes = np.bincount(code.cpu().numpy(), minlength=3).tolist()
+    h.free()
+    return {"workload": "ring2d_c6: 16,384 curved quads N=7 (256x64, exact arcs), "
+                        f"{P} points (1% outside), {nfields} f64 fields; findpts2 + findpts2_eval",
+            "value": P / (ms / 1e3), "unit": "points/s", "ms_per_step": ms,
+            "findpts2_ms": ms_loc, "setup_ms": 1e3 * setup_s,
+            "pairs_per_point": pairs / steps / P, "newton_iters_per_pair": K,
+            "alg_flops_per_findpts2": flops,
+            "findpts2_tflops": flops / (ms_loc / 1e3) / 1e12, "codes": codes}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -506,6 +576,8 @@ def main():
         print(f"# spiral: {rec['spiral']}", file=sys.stderr, flush=True)
         rec["schwarz_exchange"] = schwarz_bench(fp, w, dev, head)
         print(f"# schwarz exchange: {rec['schwarz_exchange']}", file=sys.stderr, flush=True)
+        rec["twod"] = twod_bench(fp, w, dev)
+        print(f"# 2D: {rec['twod']}", file=sys.stderr, flush=True)
     if args.serving_requests > 0:
         sv = serving_bench(fp, w, dev, head, args.serving_requests, args.serving_warmup)
         rec["serving"] = sv

@@ -256,8 +256,8 @@ struct Loc2 {
 __global__ __launch_bounds__(256) void k2_cand(Loc2 a)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.npts) return;
-    const double x = a.pts[2 * (long long)t], y = a.pts[2 * (long long)t + 1];
+    const double x = t < a.npts ? a.pts[2 * (long long)t] : NAN;
+    const double y = t < a.npts ? a.pts[2 * (long long)t + 1] : NAN;
     int n = 0;
     if (x >= a.g.lo[0] && x <= a.g.hi[0] && y >= a.g.lo[1] && y <= a.g.hi[1]) {
         const long long c = cell2(a.g, 0, x) + (long long)a.g.nc[0] * cell2(a.g, 1, y);
@@ -267,13 +267,23 @@ __global__ __launch_bounds__(256) void k2_cand(Loc2 a)
             const double *b = a.bbox + 4 * (long long)e;
             if (!(x >= b[0] && x <= b[1] && y >= b[2] && y <= b[3])) continue;
             if (ps >= 0 && a.esess && a.esess[e] == ps) continue;
-            const long long s = (long long)n * a.M + t;
-            a.cand_el[s] = e;
-            a.cand_pos[s] = atomicAdd(&a.elem_cnt[e], 1);
+            a.cand_el[(long long)n * a.M + t] = e;
             ++n;
         }
     }
-    a.ncand[t] = n;
+    // ranks in the elements from converged code (shared atomics for lanes
+    // on the same element)
+    int nmax = n;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, kWave));
+    for (int k = 0; k < nmax; ++k) {
+        const bool act = k < n;
+        const long long s = (long long)k * a.M + t;
+        const int e = act ? a.cand_el[s] : -1;
+        const int r = wave_rank(a.elem_cnt, e, act);
+        if (act) a.cand_pos[s] = r;
+    }
+    if (t < a.npts) a.ncand[t] = n;
 }
 
 __global__ __launch_bounds__(256) void k2_scatter(Loc2 a)
@@ -613,10 +623,12 @@ struct Ev2 {
 __global__ __launch_bounds__(256) void k2_ev_count(Ev2 a)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = p < a.npts ? a.el[p] : -1;
+    const bool ok = p < a.npts && a.code[p] != FP_NOT_FOUND && e >= 0 && e < a.E;
+    const int r = wave_rank(a.cnt, e, ok);  // converged: every lane of the wave
     if (p >= a.npts) return;
-    const int e = a.el[p];
-    if (a.code[p] != FP_NOT_FOUND && e >= 0 && e < a.E) {
-        a.pos[p] = atomicAdd(&a.cnt[e], 1);
+    if (ok) {
+        a.pos[p] = r;
     } else {
         a.pos[p] = -1;
         for (int f = 0; f < a.nf_all; ++f) a.out_all[f * a.ostride + p] = NAN;

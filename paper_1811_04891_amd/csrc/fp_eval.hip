@@ -36,10 +36,12 @@ struct EvArgs {
 __global__ __launch_bounds__(256) void k_ev_count(EvArgs a)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = p < a.npts ? a.el[p] : -1;
+    const bool ok = p < a.npts && a.code[p] != FP_NOT_FOUND && e >= 0 && e < a.E;
+    const int r = wave_rank(a.cnt, e, ok);  // converged: every lane of the wave
     if (p >= a.npts) return;
-    const int e = a.el[p];
-    if (a.code[p] != FP_NOT_FOUND && e >= 0 && e < a.E) {
-        a.pos[p] = atomicAdd(&a.cnt[e], 1);
+    if (ok) {
+        a.pos[p] = r;
     } else {
         a.pos[p] = -1;
         for (int f = 0; f < a.nf_all; ++f) a.out_all[f * a.ostride + p] = NAN;

@@ -193,12 +193,44 @@ struct UnitList {
     }
 };
 
-// Blocks of a unit launch over ns segments for a list of at most about
-// 2 n entries.  Pieces beyond the grid are taken by the grid-stride walk.
+// Blocks of a unit launch over ns segments for a list of about n entries:
+// one per segment plus up to 2 n / K (at most kUnitSpare) for the pieces of
+// crowded segments.  Units beyond the grid are taken by the grid-stride walk.
+constexpr long long kUnitSpare = 4096;
 inline int unit_grid(int ns, long long n, int K)
 {
-    const long long g = (long long)ns + 2 * ((n + K - 1) / K);
+    long long extra = 2 * ((n + K - 1) / K);
+    if (extra > kUnitSpare) extra = kUnitSpare;
+    const long long g = (long long)ns + extra;
     return (int)(g < 1 ? 1 : (g > 0x7fffffffLL ? 0x7fffffffLL : g));
+}
+
+// Rank of each active lane's entry in its group's counter, cnt[e] += 1 per
+// entry.  Lanes of a wavefront that share the group of the first pending
+// lane take their ranks from one atomic add (up to four such groups); any
+// other lane adds alone.  Call from converged code (every lane of the
+// wavefront), act false for lanes without an entry.  The ranks of a group are
+// distinct and fill [old count, new count).
+__device__ __forceinline__ int wave_rank(int *cnt, int e, bool act)
+{
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const unsigned long long below = (1ull << lane) - 1ull;
+    unsigned long long pending = __ballot(act);
+    int rank = 0;
+    for (int it = 0; it < 4 && pending; ++it) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int e0 = __shfl(e, leader, kWave);
+        const unsigned long long grp = __ballot(act && e == e0) & pending;
+        const int m = __popcll(grp);
+        if (m < 2) break;  // no sharing: the rest add alone
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&cnt[e0], m);
+        base = __shfl(base, leader, kWave);
+        if ((grp >> lane) & 1ull) rank = base + __popcll(grp & below);
+        pending &= ~grp;
+    }
+    if ((pending >> lane) & 1ull) rank = atomicAdd(&cnt[e], 1);
+    return rank;
 }
 constexpr int kUnitMin = 64;  // smallest K of the locate kernels
 

@@ -86,7 +86,7 @@ constexpr int kCountMask = (1 << kFullBit) - 1;
 __global__ __launch_bounds__(256) void k_cand(LocArgs a)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    int naabb = 0;
+    int naabb = 0, n = 0;
     if (t < a.npts && a.only && !a.only[t]) {
         a.ncand[t] = 0;
     } else if (t < a.npts) {
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void k_cand(LocArgs a)
         const double x0 = a.pts[3 * (long long)p], x1 = a.pts[3 * (long long)p + 1],
                      x2 = a.pts[3 * (long long)p + 2];
         const int ps = a.psess ? a.psess[p] : -1;
-        int n = 0, full = a.obb ? 0 : 1;
+        int full = a.obb ? 0 : 1;
         const Grid &g = a.g;
         // NaN fails every comparison, so non-finite points find nothing
         if (x0 >= g.lo[0] && x0 <= g.hi[0] && x1 >= g.lo[1] && x1 <= g.hi[1] &&
@@ -107,7 +107,6 @@ __global__ __launch_bounds__(256) void k_cand(LocArgs a)
             // outward-rounded binary32 box
             const float xf0 = (float)x0, xf1 = (float)x1, xf2 = (float)x2;
             int *ce = a.cand_el + t;
-            int *cp = a.cand_pos + t;
             // pass 0: oriented-box filter (first pass only); pass 1: every
             // candidate, taken when the filter left none (the point then
             // has its full candidate set and needs no second pass)
@@ -138,14 +137,27 @@ __global__ __launch_bounds__(256) void k_cand(LocArgs a)
                         if (!in) continue;
                     }
                     ce[(long long)n * a.M] = e;
-                    cp[(long long)n * a.M] = atomicAdd(&a.elem_cnt[e], 1);
                     ++n;
                 }
-                if (pass == 1 || naabb == 0) full = 1;  // the method's whole set
+                // the method's whole set: taken in pass 1, or left intact by
+                // the oriented-box filter
+                if (pass == 1 || naabb == 0 || n == naabb) full = 1;
                 if (pass == 0 && naabb == 0) break;     // nothing to take
             }
         }
         a.ncand[t] = n | (full << kFullBit);
+    }
+    // each pair's rank in its element, from converged code so that lanes
+    // sharing an element (a crowded element) share one atomic add
+    int nmax = n;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, kWave));
+    for (int k = 0; k < nmax; ++k) {
+        const bool act = k < n;
+        const long long s = (long long)k * a.M + t;
+        const int e = act ? a.cand_el[s] : -1;
+        const int r = wave_rank(a.elem_cnt, e, act);
+        if (act) a.cand_pos[s] = r;
     }
     if (a.obb) {  // the method's candidates of this block (first pass covers every point)
         __shared__ unsigned wsum[256 / kWave];
