@@ -55,6 +55,7 @@ struct fp2_handle {
     double *d_g = nullptr;
     double *d_binv = nullptr;
     double *d_basis = nullptr;
+    double *d_dnode = nullptr;  // n1 x n1: h_b'(z_a)
     unsigned long long *stats = nullptr;  // pairs solved, Newton iterations
     fp::Basis basis{};
 
@@ -443,7 +444,8 @@ struct TR2 {
 // One wavefront per work unit (up to 64 pairs of one element), one lane per
 // pair: closest mapped GLL node (ties: smallest node index), then Newton.
 template <int N1>
-__global__ __launch_bounds__(kWave) void k2_locate(Loc2 a, const double *__restrict__ basis)
+__global__ __launch_bounds__(kWave) void k2_locate(Loc2 a, const double *__restrict__ basis,
+                                                   const double *__restrict__ dnode)
 {
     constexpr int V = N1 * N1;
     const BasisPtr<double> B{as_const(basis)};
@@ -479,7 +481,27 @@ __global__ __launch_bounds__(kWave) void k2_locate(Loc2 a, const double *__restr
         const double r0[2] = {B.z(bq % N1), B.z(bq / N1)};
         TR2 t;
         t.start(r0);
+        // the first Newton step from the node's value and line sums
+        // (D = h_b'(z_a) at a n1 + b)
         bool done = !act;
+        if (act) {
+            const double *Xg = a.geom + (long long)e * 2 * V;
+            const int i0 = bq % N1, j0 = bq / N1;
+            double xn[2], Jn[4];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                double dr = 0.0, ds = 0.0;
+#pragma unroll
+                for (int m = 0; m < N1; ++m) {
+                    dr = fma(Xg[c * V + bq - i0 + m], dnode[i0 * N1 + m], dr);
+                    ds = fma(Xg[c * V + bq + N1 * (m - j0)], dnode[j0 * N1 + m], ds);
+                }
+                xn[c] = Xg[c * V + bq];
+                Jn[2 * c] = dr;
+                Jn[2 * c + 1] = ds;
+            }
+            done = t.update(xn, Jn, xs, rstop);
+        }
         while (!done) {
             double xt[2], Jt[4];
             geo2<N1>(X, B, t.rt, xt, Jt);
@@ -704,7 +726,7 @@ __global__ __launch_bounds__(kWave) void k2_eval(Ev2 a, const double *__restrict
 
 hipError_t launch_locate2(const fp2_handle *h, const Loc2 &a, int nblk, hipStream_t s)
 {
-#define FP2_LOC(N1) k2_locate<N1><<<nblk, kWave, 0, s>>>(a, h->d_basis)
+#define FP2_LOC(N1) k2_locate<N1><<<nblk, kWave, 0, s>>>(a, h->d_basis, h->d_dnode)
     FP2_SWITCH(FP2_LOC)
 #undef FP2_LOC
     return hipGetLastError();
@@ -799,9 +821,13 @@ extern "C" int findpts2_setup(fp2_handle **out, const double *x, const double *y
     FP2_HIP(dalloc2(h, &h->d_g, 4));
     FP2_HIP(dalloc2(h, &h->d_binv, (size_t)n1 * n1));
     FP2_HIP(dalloc2(h, &h->d_basis, 2 * kMaxN1));
+    FP2_HIP(dalloc2(h, &h->d_dnode, (size_t)n1 * n1));
     FP2_HIP(dalloc2(h, &h->stats, 2));
     const std::vector<double> binv = bernstein_to_nodal_inverse(N, h->basis.z);
+    const std::vector<double> dnode = node_derivatives(h->basis, N);
     FP2_HIP(hipMemcpyAsync(h->d_basis, &h->basis, sizeof(Basis), hipMemcpyHostToDevice, s));
+    FP2_HIP(hipMemcpyAsync(h->d_dnode, dnode.data(), sizeof(double) * n1 * n1,
+                           hipMemcpyHostToDevice, s));
     FP2_HIP(hipMemcpyAsync(h->d_binv, binv.data(), sizeof(double) * n1 * n1,
                            hipMemcpyHostToDevice, s));
     FP2_HIP(hipMemsetAsync(h->stats, 0, 2 * sizeof(unsigned long long), s));

@@ -120,6 +120,7 @@ struct fp_handle {
     fp::Basis basis{};
     fp::Basis32 basis32{};
     double *d_basis = nullptr;   // device copy of basis (z, wb)
+    double *d_dnode = nullptr;   // n1 x n1: h_b'(z_a) at row a, column b
     float *d_basis32 = nullptr;  // device copy of basis32
     size_t bytes = 0;
 
@@ -243,6 +244,10 @@ hipError_t scan_exclusive(const int *in, int *out, int n, int *tmp,
 // GLL nodes and barycentric weights of order N; the inverse of the
 // Bernstein-to-nodal matrix (n1 x n1, row-major), both computed on the host.
 Basis make_basis(int N);
+// Differentiation matrix at the nodes, D[a n1 + b] = h_b'(z_a), from the
+// barycentric weights (off-diagonal (wb_b / wb_a) / (z_a - z_b), diagonal
+// minus the row sum).
+std::vector<double> node_derivatives(const Basis &b, int N);
 std::vector<double> bernstein_to_nodal_inverse(int N, const double *z);
 
 // Fill n ints with a value (a kernel, so that it may be graph-captured).

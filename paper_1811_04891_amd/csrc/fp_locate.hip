@@ -383,8 +383,36 @@ __device__ __forceinline__ void store_pair(const LocArgs &a, BasisPtr<double> B,
 // matrix-core fragments would not fit in registers).
 constexpr int kUnitScalar = 64;
 
+// Map and Jacobian at GLL node nd of an element in global memory: the value
+// is the node itself, each derivative a one-dimensional sum along its line
+// (D = h_b'(z_a) at a n1 + b).
 template <int N1>
-__global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__restrict__ basis)
+__device__ __forceinline__ void node_geo_g(const double *__restrict__ X,
+                                           const double *__restrict__ D, int nd,
+                                           double (&x)[3], double (&J)[9])
+{
+    constexpr int V = N1 * N1 * N1;
+    const int i0 = nd % N1, j0 = (nd / N1) % N1, k0 = nd / (N1 * N1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double *Xc = X + c * V;
+        double dr = 0.0, ds = 0.0, dt = 0.0;
+#pragma unroll
+        for (int m = 0; m < N1; ++m) {
+            dr = fma(Xc[nd - i0 + m], D[i0 * N1 + m], dr);
+            ds = fma(Xc[nd + N1 * (m - j0)], D[j0 * N1 + m], ds);
+            dt = fma(Xc[nd + N1 * N1 * (m - k0)], D[k0 * N1 + m], dt);
+        }
+        x[c] = Xc[nd];
+        J[3 * c] = dr;
+        J[3 * c + 1] = ds;
+        J[3 * c + 2] = dt;
+    }
+}
+
+template <int N1>
+__global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__restrict__ basis,
+                                                  const double *__restrict__ dnode)
 {
     constexpr int V = N1 * N1 * N1;
     const BasisPtr<double> B{as_const(basis)};
@@ -423,7 +451,13 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
         node_rst<N1>(B, bq, r0);
         TRNewton t;
         t.start(r0);
+        // the first Newton step from the node's own value and line sums
         bool done = !act;
+        if (act) {
+            double xn[3], Jn[9];
+            node_geo_g<N1>(a.geom + (long long)e * 3 * V, dnode, bq, xn, Jn);
+            done = t.update(xn, Jn, xs, rstop);
+        }
         while (!done) {
             double xt[3], Jt[9];
             geo_eval<N1>(X, B, t.rt, xt, Jt);
@@ -582,7 +616,7 @@ static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, int
 #define FP_LAUNCH_LOCATE(N1)                                      \
     do {                                                          \
         *nblk = unit_grid(h->E, n, kUnitScalar);                  \
-        k_locate<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis);      \
+        k_locate<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_dnode); \
     } while (0)
 // mixed precision: first pass only (the second pass is binary64)
 #define FP_LAUNCH_MFMA(N1)                                                           \
@@ -592,7 +626,7 @@ static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, int
             k_locate_mixed<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_basis32); \
         } else {                                                                     \
             *nblk = unit_grid(h->E, n, kUnitMfma);                                   \
-            k_locate_mfma<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis);                \
+            k_locate_mfma<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_dnode);     \
         }                                                                            \
     } while (0)
     switch (h->n1) {

@@ -72,6 +72,24 @@ Basis make_basis(int N)
     return b;
 }
 
+std::vector<double> node_derivatives(const Basis &b, int N)
+{
+    const int n = N + 1;
+    std::vector<double> D((size_t)n * n, 0.0);
+    for (int a = 0; a < n; ++a) {
+        long double diag = 0.0L;
+        for (int c = 0; c < n; ++c) {
+            if (c == a) continue;
+            const long double v = ((long double)b.wb[c] / (long double)b.wb[a]) /
+                                  ((long double)b.z[a] - (long double)b.z[c]);
+            D[(size_t)a * n + c] = (double)v;
+            diag -= v;
+        }
+        D[(size_t)a * n + a] = (double)diag;
+    }
+    return D;
+}
+
 // Inverse of M[i][k] = C(N,k) u_i^k (1-u_i)^(N-k), u_i = (1 + z_i)/2: maps
 // nodal values to tensor-Bernstein coefficients.  Gauss-Jordan in long
 // double on the host.
@@ -509,7 +527,8 @@ static void release(fp_handle *h)
 {
     void *ptrs[] = {h->d_basis, h->d_basis32, h->geom, h->geom32, h->esize, h->bbox, h->obb,
                     h->esess, h->delta, h->cell_off, h->cell_cnt, h->cell_el, h->cell_box,
-                    h->work_mem, h->scan_tmp, h->stats, h->d_flag, h->d_g, h->d_binv};
+                    h->work_mem, h->scan_tmp, h->stats, h->d_flag, h->d_g, h->d_binv,
+                    h->d_dnode};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &t : h->timed) {
@@ -730,14 +749,18 @@ extern "C" int findpts_setup(fp_handle **out, const double *x, const double *y,
     FP_HIP_H(dalloc(h, &h->d_flag, 1));
     FP_HIP_H(dalloc(h, &h->d_g, 6));
     FP_HIP_H(dalloc(h, &h->d_binv, (size_t)(n1 * n1)));
+    FP_HIP_H(dalloc(h, &h->d_dnode, (size_t)(n1 * n1)));
     FP_HIP_H(hipMemcpyAsync(h->d_basis, &h->basis, sizeof(Basis), hipMemcpyHostToDevice, s));
     FP_HIP_H(hipMemcpyAsync(h->d_basis32, &h->basis32, sizeof(Basis32), hipMemcpyHostToDevice, s));
     FP_HIP_H(hipMemsetAsync(h->stats, 0, 4 * sizeof(unsigned long long), s));
     {
         const std::vector<double> binv = bernstein_to_nodal_inverse(N, h->basis.z);
+        const std::vector<double> dnode = node_derivatives(h->basis, N);
         FP_HIP_H(hipMemcpyAsync(h->d_binv, binv.data(), sizeof(double) * n1 * n1,
                                 hipMemcpyHostToDevice, s));
-        FP_HIP_H(hipStreamSynchronize(s));  // the host vector goes out of scope
+        FP_HIP_H(hipMemcpyAsync(h->d_dnode, dnode.data(), sizeof(double) * n1 * n1,
+                                hipMemcpyHostToDevice, s));
+        FP_HIP_H(hipStreamSynchronize(s));  // the host vectors go out of scope
     }
     if (elem_session) {
         FP_HIP_H(dalloc(h, &h->esess, E));
