@@ -99,8 +99,15 @@ def cpu_baseline(mesh, pts, fields, target_s=10.0):
     t_loc = time.perf_counter() - t
     c = om.last_stats[0] / n
     K = om.last_stats[1] / max(om.last_stats[0], 1)
+    # one core on a 20,000-point slice of the same sample
+    n1 = min(n, 20_000)
+    t = time.perf_counter()
+    c1, e1, r1, _ = om.findpts(sample[:n1], nthreads=1)
+    om.eval(c1, e1, r1, hf, nthreads=1)
+    t1 = time.perf_counter() - t
+    oracle.threads(nthreads)  # restore the thread count for later oracle calls
     return {"n": n, "seconds": t_loc, "cores": cores, "c": c, "K": K, "om": om,
-            "sample_code": code}
+            "sample_code": code, "one_core": n1 / t1}
 
 
 def serving_bench(fp, w, dev, precision, n_req, n_warm, slots=4, seed=40):
@@ -569,8 +576,26 @@ def main():
                       f"{cb['seconds']:.1f} s",
             "method_candidates_per_point": cb["c"],
             "method_newton_iters_per_candidate": cb["K"],
+            "one_core_points_per_s": cb["one_core"],
         }
     h.free()
+    # the library's plain copy kernel over 1 GiB: the achievable HBM stream rate
+    # beside the 8 TB/s datasheet figure (not in counter runs, whose only copy
+    # launches are the --copy-mib reference)
+    nb = 0 if args.copy_mib > 0 else 1 << 30
+    if nb:
+        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            fp.fp_copy(src, dst, stream)
+        ca, cb_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ca.record(stream)
+        for _ in range(5):
+            fp.fp_copy(src, dst, stream)
+        cb_.record(stream)
+        torch.cuda.synchronize()
+        rec["copy_GBps"] = 2 * nb * 5 / (ca.elapsed_time(cb_) / 1e3) / 1e9
+        del src, dst
     if not args.headline_only:
         rec["spiral"] = spiral_bench(fp, w, dev)
         print(f"# spiral: {rec['spiral']}", file=sys.stderr, flush=True)
