@@ -86,7 +86,7 @@ struct fp_handle {
     float *geom32 = nullptr;   // binary32 copy (mixed precision)
     double *esize = nullptr;   // E: h_e
     double *bbox = nullptr;    // E x 6
-    double *obb = nullptr;     // E x 18: frame Q (9, row-major, rows = axes),
+    float *obb = nullptr;      // E x 18 binary32: frame Q (9, row-major, rows = axes),
                                // centre (3), rotated lo (3), rotated hi (3)
     int *esess = nullptr;      // E or null
     double *delta = nullptr;   // E x V or null

@@ -29,7 +29,7 @@ struct LocArgs {
     const double *geom;
     const double *esize;
     const double *bbox;
-    const double *obb;   // non-null: also test the oriented box (first pass)
+    const float *obb;    // non-null: also test the oriented box (first pass)
     int *redo;           // first pass writes 1 for tasks left without an inside
                          // candidate and with a partial candidate set, else 0
     const int *only;     // non-null (second pass): tasks with only[t] != 0
@@ -125,14 +125,16 @@ __global__ __launch_bounds__(256) void k_cand(LocArgs a)
                     if (ps >= 0 && a.esess && a.esess[e] == ps) continue;
                     if (pass == 0) {
                         ++naabb;
-                        const double *o = a.obb + 18 * (long long)e;
-                        const double d0 = x0 - o[9], d1 = x1 - o[10], d2 = x2 - o[11];
+                        const float *o = a.obb + 18 * (long long)e;
+                        const double d0 = x0 - (double)o[9], d1 = x1 - (double)o[10],
+                                     d2 = x2 - (double)o[11];
                         bool in = true;
 #pragma unroll
                         for (int ax = 0; ax < 3; ++ax) {
-                            const double u =
-                                fma(o[3 * ax + 2], d2, fma(o[3 * ax + 1], d1, o[3 * ax] * d0));
-                            in = in && u >= o[12 + ax] && u <= o[15 + ax];
+                            const double u = fma((double)o[3 * ax + 2], d2,
+                                                 fma((double)o[3 * ax + 1], d1,
+                                                     (double)o[3 * ax] * d0));
+                            in = in && u >= (double)o[12 + ax] && u <= (double)o[15 + ax];
                         }
                         if (!in) continue;
                     }

@@ -245,12 +245,15 @@ __global__ __launch_bounds__(kWave) void k_bbox(const double *__restrict__ geom,
 // The rotated coordinates u = Q (x - centre) are linear in x, so the
 // Bernstein coefficients of their nodal values bound the element in that
 // frame exactly as the axis-aligned box does; any Q (orthonormal or not)
-// keeps this rigorous.  Same margin as the axis-aligned box.
+// keeps this rigorous.  Same margin as the axis-aligned box.  The record
+// is binary32 (72 bytes, half the binary64 one, for the candidate lookup's
+// memory traffic): Q and the centre are rounded first and the bounds are
+// computed for the rounded frame, then rounded outward.
 __global__ __launch_bounds__(kWave) void k_obb(const double *__restrict__ geom, int n1,
                                                const double *__restrict__ binv,
                                                const double *__restrict__ bbox,
                                                const double *__restrict__ esize,
-                                               double *__restrict__ obb)
+                                               float *__restrict__ obb)
 {
     extern __shared__ double sh[];
     const int V = n1 * n1 * n1;
@@ -296,8 +299,12 @@ __global__ __launch_bounds__(kWave) void k_obb(const double *__restrict__ geom, 
     if (!ok)
         for (int a = 0; a < 3; ++a)
             for (int c = 0; c < 3; ++c) Q[a][c] = (a == c) ? 1.0 : 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) Q[a][c] = (double)(float)Q[a][c];
     const double *bb = bbox + 6 * (long long)e;
-    const double ctr[3] = {0.5 * (bb[0] + bb[1]), 0.5 * (bb[2] + bb[3]), 0.5 * (bb[4] + bb[5])};
+    const double ctr[3] = {(double)(float)(0.5 * (bb[0] + bb[1])),
+                           (double)(float)(0.5 * (bb[2] + bb[3])),
+                           (double)(float)(0.5 * (bb[4] + bb[5]))};
     double lo[3], hi[3], amax = 0.0;
     for (int a = 0; a < 3; ++a) {
         for (int q = t; q < V; q += kWave) {
@@ -337,13 +344,17 @@ __global__ __launch_bounds__(kWave) void k_obb(const double *__restrict__ geom, 
     if (t == 0) {
         const double cabs = fmax(fabs(ctr[0]), fmax(fabs(ctr[1]), fabs(ctr[2])));
         const double m = 1e-8 * esize[e] + 1e-14 * (amax + cabs);
-        double *o = obb + 18 * (long long)e;
+        float *o = obb + 18 * (long long)e;
         for (int a = 0; a < 3; ++a)
-            for (int c = 0; c < 3; ++c) o[3 * a + c] = Q[a][c];
+            for (int c = 0; c < 3; ++c) o[3 * a + c] = (float)Q[a][c];  // exact
         for (int c = 0; c < 3; ++c) {
-            o[9 + c] = ctr[c];
-            o[12 + c] = lo[c] - m;
-            o[15 + c] = hi[c] + m;
+            o[9 + c] = (float)ctr[c];  // exact
+            const double l = lo[c] - m, u = hi[c] + m;
+            float lf = (float)l, uf = (float)u;
+            if ((double)lf > l) lf = nextafterf(lf, -INFINITY);
+            if ((double)uf < u) uf = nextafterf(uf, INFINITY);
+            o[12 + c] = lf;
+            o[15 + c] = uf;
         }
     }
 }
