@@ -625,7 +625,8 @@ static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, int
     do {                                                                             \
         if (h->precision == FP_PREC_MIXED && a.obb) {                                \
             *nblk = unit_grid(h->E, n, kUnitMixed);                                  \
-            k_locate_mixed<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_basis32); \
+            k_locate_mixed<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_basis32,  \
+                                                        h->d_dnode);                 \
         } else {                                                                     \
             *nblk = unit_grid(h->E, n, kUnitMfma);                                   \
             k_locate_mfma<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_dnode);     \
