@@ -412,3 +412,55 @@ def test_c3_interface_faces_full_size_sampled(dev):
     st = _sampled(om, pts.numpy(), g, idx, hs, psess=tags.numpy())
     _say(f"c3 full ok {st}")
     h.free()
+
+
+@pytest.mark.parametrize("N,prec", [(7, "fp64"), (7, "mixed"), (4, "fp64"), (9, "fp64"),
+                                    (15, "fp64")])
+def test_points_at_mesh_nodes(dev, N, prec):
+    """Query points that are mesh nodes: Newton ends at its start node (the
+    path that takes no matrix evaluation).  Every point is found inside, at
+    distance 0, with r equal to a GLL node triple of the returned element,
+    as in the oracle."""
+    fp = _fp()
+    _say(f"case: points at mesh nodes N={N} {prec}")
+    mesh = w.annulus_mesh(2, 6, 2, N=N)
+    hd = mesh.host()
+    rng = np.random.default_rng(70 + N)
+    idx = rng.choice(hd["x"].size, 3000, replace=False)
+    pts = np.stack([hd["x"].reshape(-1)[idx], hd["y"].reshape(-1)[idx],
+                    hd["z"].reshape(-1)[idx]], 1)
+    md = mesh.to(dev)
+    h = fp.findpts_setup(md.x, md.y, md.z, N, tol=TOL, max_points=4096,
+                         precision=fp.FP_PREC_MIXED if prec == "mixed" else fp.FP_PREC_FP64)
+    code, el, rst, d2 = fp.findpts(h, torch.as_tensor(pts).to(dev))
+    torch.cuda.synchronize()
+    g = (code.cpu().numpy(), el.cpu().numpy(), rst.cpu().numpy(), d2.cpu().numpy())
+    om = oracle.OracleMesh.from_mesh(mesh, TOL)
+    _, hs = om.bbox()
+    compare_locate(om, pts, g, om.findpts(pts), hs, TOL)
+    assert np.all(g[0] == 0)
+    z = w.gll_points(N)
+    assert np.all(np.min(np.abs(g[2][:, :, None] - z[None, None, :]), axis=2) <= 1e-12)
+    h.free()
+
+
+def test_points_at_mesh_nodes_2d(dev):
+    fp = _fp()
+    _say("case: 2D points at mesh nodes")
+    m = w.annulus2d_mesh(3, 10, N=7)
+    hd = m.host()
+    rng = np.random.default_rng(77)
+    idx = rng.choice(hd["x"].size, 1500, replace=False)
+    pts = np.stack([hd["x"].reshape(-1)[idx], hd["y"].reshape(-1)[idx]], 1)
+    md = m.to(dev)
+    h = fp.findpts2_setup(md.x, md.y, m.N, tol=TOL)
+    code, el, rs, d2 = fp.findpts2(h, torch.as_tensor(pts).to(dev))
+    torch.cuda.synchronize()
+    g = (code.cpu().numpy(), el.cpu().numpy(), rs.cpu().numpy(), d2.cpu().numpy())
+    om = oracle.OracleMesh2.from_mesh(m, TOL)
+    _, hs = om.bbox()
+    compare_locate(om, pts, g, om.findpts(pts), hs, TOL)
+    assert np.all(g[0] == 0)
+    z = w.gll_points(7)
+    assert np.all(np.min(np.abs(g[2][:, :, None] - z[None, None, :]), axis=2) <= 1e-12)
+    h.free()
