@@ -356,7 +356,7 @@ def twod_bench(fp, w, dev, steps=20, warmup=3, nfields=4):
     b.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / steps
-    pairs, iters = fp.findpts2_stats(h)
+    pairs, iters, cands = fp.findpts2_stats(h)
     a.record()
     for _ in range(steps):
         locate()
@@ -372,6 +372,7 @@ def twod_bench(fp, w, dev, steps=20, warmup=3, nfields=4):
             "value": P / (ms / 1e3), "unit": "points/s", "ms_per_step": ms,
             "findpts2_ms": ms_loc, "setup_ms": 1e3 * setup_s,
             "pairs_per_point": pairs / steps / P, "newton_iters_per_pair": K,
+            "method_candidates_per_point": cands / steps / P,
             "alg_flops_per_findpts2": flops,
             "findpts2_tflops": flops / (ms_loc / 1e3) / 1e12, "codes": codes}
 

@@ -203,7 +203,8 @@ FP_API int findpts_free(fp_handle *h);
  * of element e is at flat index i + (N+1) (j + (N+1) e).  Readings as in three
  * dimensions: Bernstein-hull boxes with the same margin, h_e = largest
  * per-axis node extent, closest-node start (smallest index on ties), the same
- * trust-region rules on [-1,1]^2, the same classification and selection.
+ * trust-region rules on [-1,1]^2, the same classification and selection (and,
+ * as in 3D, an oriented-box first round that never changes a result).
  *
  * findpts2_setup -- like findpts_setup: x, y hold E*(N+1)^2 doubles each,
  * elem_session E ints or NULL, delta E*(N+1)^2 doubles or NULL; all device
@@ -234,8 +235,9 @@ FP_API int findpts2_eval(fp2_handle *h, int npts, const int *code, const int *el
                          const double *rs, int nfields, const double *const *h_fields,
                          double *out, void *stream);
 
-/* Pairs solved and Newton iterations since setup (h_counts: 2 host long
- * longs); reset != 0 zeroes them.  Synchronous. */
+/* Since setup (h_counts: 3 host long longs): pairs solved, Newton
+ * iterations, and the method's candidates (hash + axis-aligned box +
+ * session test); reset != 0 zeroes them.  Synchronous. */
 FP_API int findpts2_stats(fp2_handle *h, long long *h_counts, int reset);
 
 /* Element boxes (host E*4 doubles: xmin xmax ymin ymax) and sizes h_e (host E

@@ -5,9 +5,14 @@
 //
 // Setup: packed element blocks (E x 2 x n1^2), Bernstein-hull boxes and h_e
 // (one wavefront per element), a uniform hash grid of about 4 E cells with
-// ascending element lists.  findpts2, per pass of at most max_points points:
-//   k2_cand     per point: cell, box and session test, candidate list and each
-//               pair's rank in its element
+// ascending element lists, and an oriented box per element.  findpts2, per
+// pass of at most max_points points, in two rounds like the 3D path (first
+// the candidates whose oriented box holds the point; then, for points left
+// without an inside candidate whose list the oriented boxes cut, the whole
+// axis-aligned set):
+//   k2_cand     per point: cell, box and session test (and the oriented box
+//               in the first round), candidate list and each pair's rank in
+//               its element
 //   scan        pair counts per element -> offsets; k2_scatter groups pairs
 //   k2_locate   one wavefront per work unit (up to 64 pairs of one element):
 //               closest mapped node (node rows by scalar loads), trust-region
@@ -34,6 +39,8 @@ struct fp2_handle {
     double *geom = nullptr;   // E x 2 x V
     double *esize = nullptr;  // E
     double *bbox = nullptr;   // E x 4: xmin xmax ymin ymax
+    float *obb = nullptr;     // E x 10 binary32: frame Q (2 x 2, rows = axes), centre (2),
+                              // rotated lo (2), rotated hi (2)
     int *esess = nullptr;     // E or null
     double *delta = nullptr;  // E x V or null
     double glo[2] = {0, 0}, ghi[2] = {0, 0}, ginv[2] = {0, 0};
@@ -49,6 +56,8 @@ struct fp2_handle {
     int *res_in = nullptr;
     double *res_dl = nullptr;
     unsigned *iter_part = nullptr;
+    unsigned *cand_part = nullptr;  // per k2_cand block: axis-aligned candidates
+    int *redo = nullptr;            // M: second-round flag per point
     int *ev_pos = nullptr, *ev_order = nullptr;
     int *scan_tmp = nullptr;
     int *d_flag = nullptr;
@@ -56,7 +65,7 @@ struct fp2_handle {
     double *d_binv = nullptr;
     double *d_basis = nullptr;
     double *d_dnode = nullptr;  // n1 x n1: h_b'(z_a)
-    unsigned long long *stats = nullptr;  // pairs solved, Newton iterations
+    unsigned long long *stats = nullptr;  // pairs solved, Newton iterations, method candidates
     fp::Basis basis{};
 
     std::vector<void *> allocs;
@@ -153,6 +162,103 @@ __global__ __launch_bounds__(kWave) void k2_bbox(const double *__restrict__ geom
     }
 }
 
+// Oriented box of each element (one wavefront per element): frame from the
+// mean edge vectors along r and s (Gram-Schmidt; identity if degenerate),
+// rounded to binary32 with the centre before the Bernstein hull of the
+// rotated coordinates u = Q (x - centre) is taken, so the box holds the
+// element for the stored frame; same margin as the axis-aligned box, bounds
+// rounded outward.
+__global__ __launch_bounds__(kWave) void k2_obb(const double *__restrict__ geom, int n1,
+                                                const double *__restrict__ binv,
+                                                const double *__restrict__ bbox,
+                                                const double *__restrict__ esize,
+                                                float *__restrict__ obb)
+{
+    __shared__ double A[kMaxN1 * kMaxN1], Bc[kMaxN1 * kMaxN1], Bi[kMaxN1 * kMaxN1];
+    const int e = blockIdx.x, t = threadIdx.x, V = n1 * n1;
+    for (int q = t; q < V; q += kWave) Bi[q] = binv[q];
+    const double *X = geom + (long long)e * 2 * V;
+    double ed[2][2];
+    for (int c = 0; c < 2; ++c) {
+        double sr = 0.0, ss = 0.0;
+        for (int q = t; q < n1; q += kWave) {
+            sr += X[c * V + n1 - 1 + n1 * q] - X[c * V + n1 * q];
+            ss += X[c * V + q + n1 * (n1 - 1)] - X[c * V + q];
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            sr += __shfl_xor(sr, o, kWave);
+            ss += __shfl_xor(ss, o, kWave);
+        }
+        ed[0][c] = sr;
+        ed[1][c] = ss;
+    }
+    double Q[2][2];
+    bool ok = true;
+    for (int a = 0; a < 2; ++a) {
+        double v[2] = {ed[a][0], ed[a][1]};
+        if (a == 1) {
+            const double d = v[0] * Q[0][0] + v[1] * Q[0][1];
+            v[0] -= d * Q[0][0];
+            v[1] -= d * Q[0][1];
+        }
+        const double nv = sqrt(v[0] * v[0] + v[1] * v[1]);
+        const double ne = sqrt(ed[a][0] * ed[a][0] + ed[a][1] * ed[a][1]);
+        ok = ok && isfinite(nv) && nv > 1e-6 * ne && ne > 0.0;
+        Q[a][0] = ok ? v[0] / nv : 0.0;
+        Q[a][1] = ok ? v[1] / nv : 0.0;
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int c = 0; c < 2; ++c) Q[a][c] = (double)(float)(ok ? Q[a][c] : (a == c ? 1.0 : 0.0));
+    const double *bb = bbox + 4 * (long long)e;
+    const double ctr[2] = {(double)(float)(0.5 * (bb[0] + bb[1])),
+                           (double)(float)(0.5 * (bb[2] + bb[3]))};
+    double lo[2], hi[2], amax = 0.0;
+    for (int a = 0; a < 2; ++a) {
+        for (int q = t; q < V; q += kWave) {
+            const double u = Q[a][0] * (X[q] - ctr[0]) + Q[a][1] * (X[V + q] - ctr[1]);
+            A[q] = u;
+            amax = fmax(amax, fabs(u));
+        }
+        __syncthreads();
+        for (int q = t; q < V; q += kWave) {  // along r
+            const int i = q % n1, j = q / n1;
+            double sum = 0.0;
+            for (int l = 0; l < n1; ++l) sum = fma(Bi[i * n1 + l], A[j * n1 + l], sum);
+            Bc[q] = sum;
+        }
+        __syncthreads();
+        double cmn = INFINITY, cmx = -INFINITY;
+        for (int q = t; q < V; q += kWave) {  // along s
+            const int i = q % n1, j = q / n1;
+            double sum = 0.0;
+            for (int l = 0; l < n1; ++l) sum = fma(Bi[j * n1 + l], Bc[i + n1 * l], sum);
+            cmn = fmin(cmn, sum);
+            cmx = fmax(cmx, sum);
+        }
+        lo[a] = wave_min2(cmn);
+        hi[a] = wave_max2(cmx);
+        __syncthreads();
+    }
+    amax = wave_max2(amax);
+    if (t == 0) {
+        const double cabs = fmax(fabs(ctr[0]), fabs(ctr[1]));
+        const double m = 1e-8 * esize[e] + 1e-14 * (amax + cabs);
+        float *o = obb + 10 * (long long)e;
+        for (int a = 0; a < 2; ++a)
+            for (int c = 0; c < 2; ++c) o[2 * a + c] = (float)Q[a][c];  // exact
+        for (int c = 0; c < 2; ++c) {
+            o[4 + c] = (float)ctr[c];  // exact
+            const double l = lo[c] - m, u = hi[c] + m;
+            float lf = (float)l, uf = (float)u;
+            if ((double)lf > l) lf = nextafterf(lf, -INFINITY);
+            if ((double)uf < u) uf = nextafterf(uf, INFINITY);
+            o[6 + c] = lf;
+            o[8 + c] = uf;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k2_gbox(const double *__restrict__ bbox, int E,
                                                double *__restrict__ out)
 {
@@ -237,7 +343,14 @@ __global__ __launch_bounds__(256) void k2_hash_sort(const int *__restrict__ off,
     atomicMax(maxlen, n);
 }
 
+constexpr int kFull2 = 30;  // ncand bit: the list is the method's whole set
+constexpr int kCount2 = (1 << kFull2) - 1;
+
 struct Loc2 {
+    const float *obb;  // non-null: first round (oriented boxes)
+    int *redo;         // first round writes the second-round flags
+    const int *only;   // non-null: second round, points with only[t] != 0
+    unsigned *cand_part;
     const double *geom, *esize, *bbox, *delta, *pts;
     const int *esess, *cell_off, *cell_el, *psess;
     Grid2 g;
@@ -253,23 +366,40 @@ struct Loc2 {
 };
 
 // Candidates of each point: hash cell, then the closed box, then session
-// exclusion; ascending element ids (the cell lists are sorted).
+// exclusion; ascending element ids (the cell lists are sorted).  First
+// round: only those whose oriented box holds the point, or every one if none
+// does (then, or when the filter dropped nothing, the list is the whole set).
 __global__ __launch_bounds__(256) void k2_cand(Loc2 a)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const double x = t < a.npts ? a.pts[2 * (long long)t] : NAN;
-    const double y = t < a.npts ? a.pts[2 * (long long)t + 1] : NAN;
-    int n = 0;
+    const bool skip = t >= a.npts || (a.only && !a.only[t]);
+    const double x = skip ? NAN : a.pts[2 * (long long)t];
+    const double y = skip ? NAN : a.pts[2 * (long long)t + 1];
+    int n = 0, naabb = 0, full = a.obb ? 0 : 1;
     if (x >= a.g.lo[0] && x <= a.g.hi[0] && y >= a.g.lo[1] && y <= a.g.hi[1]) {
         const long long c = cell2(a.g, 0, x) + (long long)a.g.nc[0] * cell2(a.g, 1, y);
         const int ps = a.psess ? a.psess[t] : -1;
-        for (int q = a.cell_off[c]; q < a.cell_off[c + 1] && n < a.MC; ++q) {
-            const int e = a.cell_el[q];
-            const double *b = a.bbox + 4 * (long long)e;
-            if (!(x >= b[0] && x <= b[1] && y >= b[2] && y <= b[3])) continue;
-            if (ps >= 0 && a.esess && a.esess[e] == ps) continue;
-            a.cand_el[(long long)n * a.M + t] = e;
-            ++n;
+        for (int pass = a.obb ? 0 : 1; pass < 2 && n == 0; ++pass) {
+            for (int q = a.cell_off[c]; q < a.cell_off[c + 1] && n < a.MC; ++q) {
+                const int e = a.cell_el[q];
+                const double *b = a.bbox + 4 * (long long)e;
+                if (!(x >= b[0] && x <= b[1] && y >= b[2] && y <= b[3])) continue;
+                if (ps >= 0 && a.esess && a.esess[e] == ps) continue;
+                if (pass == 0) {
+                    ++naabb;
+                    const float *o = a.obb + 10 * (long long)e;
+                    const double d0 = x - (double)o[4], d1 = y - (double)o[5];
+                    const double u0 = fma((double)o[1], d1, (double)o[0] * d0);
+                    const double u1 = fma((double)o[3], d1, (double)o[2] * d0);
+                    if (!(u0 >= (double)o[6] && u0 <= (double)o[8] && u1 >= (double)o[7] &&
+                          u1 <= (double)o[9]))
+                        continue;
+                }
+                a.cand_el[(long long)n * a.M + t] = e;
+                ++n;
+            }
+            if (pass == 1 || naabb == 0 || n == naabb) full = 1;
+            if (pass == 0 && naabb == 0) break;
         }
     }
     // ranks in the elements from converged code (shared atomics for lanes
@@ -284,14 +414,27 @@ __global__ __launch_bounds__(256) void k2_cand(Loc2 a)
         const int r = wave_rank(a.elem_cnt, e, act);
         if (act) a.cand_pos[s] = r;
     }
-    if (t < a.npts) a.ncand[t] = n;
+    if (t < a.npts) a.ncand[t] = n | (full << kFull2);
+    if (a.obb) {  // the method's candidates of this block (the first round sees every point)
+        __shared__ unsigned wsum[256 / kWave];
+        unsigned v = (unsigned)naabb;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+        if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned b = 0;
+            for (int i = 0; i < 256 / kWave; ++i) b += wsum[i];
+            a.cand_part[blockIdx.x] = b;
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k2_scatter(Loc2 a)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.npts) return;
-    const int n = a.ncand[t];
+    const int n = a.ncand[t] & kCount2;
     for (int k = 0; k < n; ++k) {
         const long long s = (long long)k * a.M + t;
         a.order[a.elem_off[a.cand_el[s]] + a.cand_pos[s]] = (int)s;
@@ -549,8 +692,10 @@ __global__ __launch_bounds__(256) void k2_select(Loc2 a, int *__restrict__ code,
                                                  double *__restrict__ dist2)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.npts) return;
-    const int n = a.ncand[t];
+    if (t >= a.npts || (a.only && !a.only[t])) return;  // second round: flagged points
+    const int nv = a.ncand[t];
+    const int n = nv & kCount2;
+    const bool full = (nv >> kFull2) != 0;
     auto S = [&](int k) { return (long long)k * a.M + t; };
     int w = -1, c = 2;
     bool anyin = false;
@@ -606,23 +751,36 @@ __global__ __launch_bounds__(256) void k2_select(Loc2 a, int *__restrict__ code,
         rs[2 * (long long)t + 1] = o[1];
         dist2[t] = o[2];
     }
+    if (a.obb) a.redo[t] = (c != 0 && !full) ? 1 : 0;
 }
 
-__global__ __launch_bounds__(1024) void k2_stats(const unsigned *iter_part, int ni, int E,
+__global__ __launch_bounds__(1024) void k2_stats(const unsigned *iter_part, int ni,
+                                                 const unsigned *cand_part, int nb, int E,
                                                  const int *elem_off, unsigned long long *stats)
 {
-    __shared__ unsigned long long si[1024 / kWave];
-    unsigned long long it = 0;
+    __shared__ unsigned long long si[1024 / kWave], sc[1024 / kWave];
+    unsigned long long it = 0, c = 0;
     for (int i = threadIdx.x; i < ni; i += blockDim.x) it += iter_part[i];
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) c += cand_part[i];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) it += __shfl_xor(it, o, kWave);
-    if ((threadIdx.x & (kWave - 1)) == 0) si[threadIdx.x / kWave] = it;
+    for (int o = 32; o > 0; o >>= 1) {
+        it += __shfl_xor(it, o, kWave);
+        c += __shfl_xor(c, o, kWave);
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        si[threadIdx.x / kWave] = it;
+        sc[threadIdx.x / kWave] = c;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long I = 0;
-        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) I += si[w];
+        unsigned long long I = 0, Cn = 0;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+            I += si[w];
+            Cn += sc[w];
+        }
         atomicAdd(&stats[0], (unsigned long long)elem_off[E]);
         atomicAdd(&stats[1], I);
+        if (Cn) atomicAdd(&stats[2], Cn);
     }
 }
 
@@ -817,12 +975,13 @@ extern "C" int findpts2_setup(fp2_handle **out, const double *x, const double *y
     FP2_HIP(dalloc2(h, &h->geom, 2 * (size_t)EV));
     FP2_HIP(dalloc2(h, &h->esize, (size_t)E));
     FP2_HIP(dalloc2(h, &h->bbox, 4 * (size_t)E));
+    FP2_HIP(dalloc2(h, &h->obb, 10 * (size_t)E));
     FP2_HIP(dalloc2(h, &h->d_flag, 1));
     FP2_HIP(dalloc2(h, &h->d_g, 4));
     FP2_HIP(dalloc2(h, &h->d_binv, (size_t)n1 * n1));
     FP2_HIP(dalloc2(h, &h->d_basis, 2 * kMaxN1));
     FP2_HIP(dalloc2(h, &h->d_dnode, (size_t)n1 * n1));
-    FP2_HIP(dalloc2(h, &h->stats, 2));
+    FP2_HIP(dalloc2(h, &h->stats, 3));
     const std::vector<double> binv = bernstein_to_nodal_inverse(N, h->basis.z);
     const std::vector<double> dnode = node_derivatives(h->basis, N);
     FP2_HIP(hipMemcpyAsync(h->d_basis, &h->basis, sizeof(Basis), hipMemcpyHostToDevice, s));
@@ -830,7 +989,7 @@ extern "C" int findpts2_setup(fp2_handle **out, const double *x, const double *y
                            hipMemcpyHostToDevice, s));
     FP2_HIP(hipMemcpyAsync(h->d_binv, binv.data(), sizeof(double) * n1 * n1,
                            hipMemcpyHostToDevice, s));
-    FP2_HIP(hipMemsetAsync(h->stats, 0, 2 * sizeof(unsigned long long), s));
+    FP2_HIP(hipMemsetAsync(h->stats, 0, 3 * sizeof(unsigned long long), s));
     if (elem_session) {
         FP2_HIP(dalloc2(h, &h->esess, (size_t)E));
         FP2_HIP(hipMemcpyAsync(h->esess, elem_session, sizeof(int) * E, hipMemcpyDeviceToDevice, s));
@@ -846,6 +1005,8 @@ extern "C" int findpts2_setup(fp2_handle **out, const double *x, const double *y
         FP2_HIP(hipGetLastError());
     }
     k2_bbox<<<E, kWave, 0, s>>>(h->geom, n1, h->d_binv, h->bbox, h->esize);
+    FP2_HIP(hipGetLastError());
+    k2_obb<<<E, kWave, 0, s>>>(h->geom, n1, h->d_binv, h->bbox, h->esize, h->obb);
     FP2_HIP(hipGetLastError());
     k2_gbox<<<1, 256, 0, s>>>(h->bbox, E, h->d_g);
     FP2_HIP(hipGetLastError());
@@ -920,6 +1081,8 @@ extern "C" int findpts2_setup(fp2_handle **out, const double *x, const double *y
     if (delta) FP2_HIP(dalloc2(h, &h->res_dl, M * MC));
     FP2_HIP(dalloc2(h, &h->iter_part, (size_t)unit_grid(E, (long long)M, kUnit2)));
     FP2_HIP(dalloc2(h, &h->ev_pos, M));
+    FP2_HIP(dalloc2(h, &h->redo, M));
+    FP2_HIP(dalloc2(h, &h->cand_part, (M + 255) / 256));
     FP2_HIP(dalloc2(h, &h->ev_order, M));
     FP2_HIP(hipStreamSynchronize(s));
     *out = h;
@@ -979,20 +1142,27 @@ extern "C" int findpts2(fp2_handle *h, int npts, const double *pts, const int *p
         a.res_in = h->res_in;
         a.res_dl = h->res_dl;
         a.iter_part = h->iter_part;
+        a.cand_part = h->cand_part;
         const int pb = (n + 255) / 256;
-        FP_HIP(fill_int(h->elem_cnt, 0, (long long)h->E + 1, s));
-        k2_cand<<<pb, 256, 0, s>>>(a);
-        FP_HIP(hipGetLastError());
-        FP_HIP(scan_exclusive(h->elem_cnt, h->elem_off, h->E, h->scan_tmp, s));
-        k2_scatter<<<pb, 256, 0, s>>>(a);
-        FP_HIP(hipGetLastError());
-        const int nblk = unit_grid(h->E, n, kUnit2);
-        FP_HIP(launch_locate2(h, a, nblk, s));
-        k2_select<<<pb, 256, 0, s>>>(a, code + start, el + start, rs + 2 * (long long)start,
-                                     dist2 + start);
-        FP_HIP(hipGetLastError());
-        k2_stats<<<1, 1024, 0, s>>>(h->iter_part, nblk, h->E, h->elem_off, h->stats);
-        FP_HIP(hipGetLastError());
+        for (int round = 0; round < 2; ++round) {
+            a.obb = round == 0 ? h->obb : nullptr;
+            a.redo = round == 0 ? h->redo : nullptr;
+            a.only = round == 0 ? nullptr : h->redo;
+            FP_HIP(fill_int(h->elem_cnt, 0, (long long)h->E + 1, s));
+            k2_cand<<<pb, 256, 0, s>>>(a);
+            FP_HIP(hipGetLastError());
+            FP_HIP(scan_exclusive(h->elem_cnt, h->elem_off, h->E, h->scan_tmp, s));
+            k2_scatter<<<pb, 256, 0, s>>>(a);
+            FP_HIP(hipGetLastError());
+            const int nblk = unit_grid(h->E, n, kUnit2);
+            FP_HIP(launch_locate2(h, a, nblk, s));
+            k2_select<<<pb, 256, 0, s>>>(a, code + start, el + start, rs + 2 * (long long)start,
+                                         dist2 + start);
+            FP_HIP(hipGetLastError());
+            k2_stats<<<1, 1024, 0, s>>>(h->iter_part, nblk, h->cand_part, round == 0 ? pb : 0,
+                                        h->E, h->elem_off, h->stats);
+            FP_HIP(hipGetLastError());
+        }
     }
     return FP_OK;
 }
@@ -1064,10 +1234,9 @@ extern "C" int findpts2_stats(fp2_handle *h, long long *h_counts, int reset)
         set_error("findpts2_stats: NULL argument");
         return FP_EINVAL;
     }
-    unsigned long long v[2];
+    unsigned long long v[3];
     FP_HIP(hipMemcpy(v, h->stats, sizeof v, hipMemcpyDeviceToHost));
-    h_counts[0] = (long long)v[0];
-    h_counts[1] = (long long)v[1];
+    for (int i = 0; i < 3; ++i) h_counts[i] = (long long)v[i];
     if (reset) FP_HIP(hipMemset(h->stats, 0, sizeof v));
     return FP_OK;
 }

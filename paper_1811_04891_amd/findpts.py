@@ -475,8 +475,8 @@ def findpts2_eval(h: Handle2, code: torch.Tensor, el: torch.Tensor, rs: torch.Te
 
 
 def findpts2_stats(h: Handle2, reset: bool = False):
-    """(pairs solved, Newton iterations) since setup/reset."""
-    v = (C.c_longlong * 2)()
+    """(pairs solved, Newton iterations, method candidates) since setup/reset."""
+    v = (C.c_longlong * 3)()
     _check(lib().findpts2_stats(h.ptr, v, int(bool(reset))), "findpts2_stats")
     return tuple(v)
 
