@@ -30,6 +30,8 @@ struct LocArgs {
     const double *esize;
     const double *bbox;
     const float *obb;    // non-null: also test the oriented box (first pass)
+    const float *obb2;   // second pass: the oriented boxes, to find the candidates
+                         // the first pass dropped
     int *redo;           // first pass writes 1 for tasks left without an inside
                          // candidate and with a partial candidate set, else 0
     const int *only;     // non-null (second pass): tasks with only[t] != 0
@@ -82,11 +84,14 @@ constexpr int kCountMask = (1 << kFullBit) - 1;
 // the session exclusion (the method's candidate set), then, in the first
 // pass, the oriented box.  The oriented box holds the whole element, so it
 // never drops an element that contains the point; points left without an
-// inside candidate are redone with the axis-aligned set alone.
+// inside candidate get, in the second pass, the candidates the first pass
+// dropped, appended after its own (whose results stay; a pair the binary32
+// phase left unsolved is solved again in its slot).  cand_pos = -1 marks a
+// slot that keeps its first-pass result.
 __global__ __launch_bounds__(256) void k_cand(LocArgs a)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    int naabb = 0, n = 0;
+    int naabb = 0, n = 0, n1st = 0;
     if (t < a.npts && a.only && !a.only[t]) {
         a.ncand[t] = 0;
     } else if (t < a.npts) {
@@ -95,6 +100,10 @@ __global__ __launch_bounds__(256) void k_cand(LocArgs a)
                      x2 = a.pts[3 * (long long)p + 2];
         const int ps = a.psess ? a.psess[p] : -1;
         int full = a.obb ? 0 : 1;
+        if (a.only) {  // second pass: the first pass's candidates stay in their slots
+            n1st = a.ncand[t] & kCountMask;
+            n = n1st;
+        }
         const Grid &g = a.g;
         // NaN fails every comparison, so non-finite points find nothing
         if (x0 >= g.lo[0] && x0 <= g.hi[0] && x1 >= g.lo[1] && x1 <= g.hi[1] &&
@@ -110,7 +119,7 @@ __global__ __launch_bounds__(256) void k_cand(LocArgs a)
             // pass 0: oriented-box filter (first pass only); pass 1: every
             // candidate, taken when the filter left none (the point then
             // has its full candidate set and needs no second pass)
-            for (int pass = a.obb ? 0 : 1; pass < 2 && n == 0; ++pass) {
+            for (int pass = a.obb ? 0 : 1; pass < 2 && (n == 0 || a.only); ++pass) {
                 for (int q = qb; q < qe; ++q) {
                     // binary32 box (outward-rounded: a superset), then the
                     // exact binary64 box of the method
@@ -123,9 +132,9 @@ __global__ __launch_bounds__(256) void k_cand(LocArgs a)
                     if (x0 < b[0] || x0 > b[1] || x1 < b[2] || x1 > b[3] || x2 < b[4] || x2 > b[5])
                         continue;
                     if (ps >= 0 && a.esess && a.esess[e] == ps) continue;
-                    if (pass == 0) {
+                    if (pass == 0 || a.only) {
                         ++naabb;
-                        const float *o = a.obb + 18 * (long long)e;
+                        const float *o = (a.only ? a.obb2 : a.obb) + 18 * (long long)e;
                         const double d0 = x0 - (double)o[9], d1 = x1 - (double)o[10],
                                      d2 = x2 - (double)o[11];
                         bool in = true;
@@ -136,7 +145,7 @@ __global__ __launch_bounds__(256) void k_cand(LocArgs a)
                                                      (double)o[3 * ax] * d0));
                             in = in && u >= (double)o[12 + ax] && u <= (double)o[15 + ax];
                         }
-                        if (!in) continue;
+                        if (in == (a.only != nullptr)) continue;  // second pass: the dropped
                     }
                     ce[(long long)n * a.M] = e;
                     ++n;
@@ -155,11 +164,12 @@ __global__ __launch_bounds__(256) void k_cand(LocArgs a)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, kWave));
     for (int k = 0; k < nmax; ++k) {
-        const bool act = k < n;
         const long long s = (long long)k * a.M + t;
+        // a first-pass slot is solved again only if it was left unsolved
+        const bool act = k < n && (k >= n1st || a.res_in[s] == kUnsolved);
         const int e = act ? a.cand_el[s] : -1;
         const int r = wave_rank(a.elem_cnt, e, act);
-        if (act) a.cand_pos[s] = r;
+        if (k < n) a.cand_pos[s] = act ? r : -1;
     }
     if (a.obb) {  // the method's candidates of this block (first pass covers every point)
         __shared__ unsigned wsum[256 / kWave];
@@ -183,8 +193,8 @@ __global__ __launch_bounds__(256) void k_scatter(LocArgs a)
     const int n = a.ncand[p] & kCountMask;  // 0 for tasks the pass skips
     for (int k = 0; k < n; ++k) {
         const long long s = (long long)k * a.M + p;
-        const int e = a.cand_el[s];
-        a.order[a.elem_off[e] + a.cand_pos[s]] = (int)s;
+        const int r = a.cand_pos[s];
+        if (r >= 0) a.order[a.elem_off[a.cand_el[s]] + r] = (int)s;
     }
 }
 
@@ -512,7 +522,8 @@ __global__ __launch_bounds__(1024) void k_stats(const unsigned *cand_part, int n
     }
 }
 
-// Owner selection per point (candidates are in ascending element order).
+// Owner selection per point; ownership and ties go by explicit element ids
+// (the second pass appends the candidates the first dropped, unsorted).
 __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ code,
                                                 int *__restrict__ el, double *__restrict__ rst,
                                                 double *__restrict__ dist2)
@@ -554,14 +565,14 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
                     bs = sk;
                 }
             }
-            for (int k = 0; k < n && w < 0; ++k) {
+            for (int k = 0; k < n; ++k) {
                 if (a.res_in[S(k)] != 1) continue;
                 const int sk = a.esess ? a.esess[a.cand_el[S(k)]] : 0;
-                if (sk == bs) w = k;
+                if (sk == bs && (w < 0 || a.cand_el[S(k)] < a.cand_el[S(w)])) w = k;
             }
         } else {
-            for (int k = 0; k < n && w < 0; ++k)
-                if (a.res_in[S(k)] == 1) w = k;
+            for (int k = 0; k < n; ++k)
+                if (a.res_in[S(k)] == 1 && (w < 0 || a.cand_el[S(k)] < a.cand_el[S(w)])) w = k;
         }
     } else if (unsolved) {
         c = 1;  // provisional: the second pass decides
@@ -571,7 +582,9 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
         for (int k = 1; k < n; ++k) {
             const double dk = a.res[4 * (S(k)) + 3], dw = a.res[4 * (S(w)) + 3];
             const bool tie = fabs(dk - dw) <= 1e-14 * fmax(dk, dw);
-            if (!tie && dk < dw) w = k;  // ties keep the earlier (smaller) id
+            // ties go to the smaller element id (the second pass appends the
+            // candidates the first dropped, so the list is not sorted)
+            if ((!tie && dk < dw) || (tie && a.cand_el[S(k)] < a.cand_el[S(w)])) w = k;
         }
     }
     code[p] = c;
@@ -732,6 +745,7 @@ int run_findpts(fp_handle *h, const Work &w, int npts, const double *pts, const 
         // second pass over the flagged tasks with the axis-aligned candidates
         // only (other tasks get no candidates and keep their result)
         a.obb = nullptr;
+        a.obb2 = h->obb;
         a.redo = nullptr;
         a.only = w.redo;
         FP_HIP(fill_int(w.elem_cnt, 0, (long long)h->E + 1, s));
