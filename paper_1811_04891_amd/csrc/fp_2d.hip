@@ -593,10 +593,10 @@ __global__ __launch_bounds__(kWave) void k2_locate(Loc2 a, const double *__restr
     constexpr int V = N1 * N1;
     const BasisPtr<double> B{as_const(basis)};
     unsigned long long my_iters = 0;
-    const UnitList L(a.elem_off, a.E, 1, a.E, kUnit2);
-    for (long long u = blockIdx.x; u < L.end; u += gridDim.x) {
+    const UnitList units(a.elem_off, a.E, 1, a.E, kUnit2);
+    for (long long u = blockIdx.x; u < units.end; u += gridDim.x) {
         Unit U;
-        if (!L.at(u, U)) continue;
+        if (!units.at(u, U)) continue;
         const int e = U.seg;
         cptr<double> X = as_const(a.geom + (long long)e * 2 * V);
         const double he = a.esize[e];
@@ -832,10 +832,10 @@ __global__ __launch_bounds__(kWave) void k2_eval(Ev2 a, const double *__restrict
 {
     constexpr int V = N1 * N1;
     const BasisPtr<double> B{as_const(basis)};
-    const UnitList L(a.off, a.E, 1, a.E, kUnitEval2);
-    for (long long u = blockIdx.x; u < L.end; u += gridDim.x) {
+    const UnitList units(a.off, a.E, 1, a.E, kUnitEval2);
+    for (long long u = blockIdx.x; u < units.end; u += gridDim.x) {
         Unit U;
-        if (!L.at(u, U)) continue;
+        if (!units.at(u, U)) continue;
         const int e = U.seg;
         for (int base = U.beg; base < U.end; base += kWave) {
             const int q = base + (int)threadIdx.x;

@@ -65,10 +65,10 @@ __global__ __launch_bounds__(kWave) void k_eval(EvArgs a, FieldPtrs F, const dou
 {
     constexpr int V = N1 * N1 * N1;
     const BasisPtr<double> B{as_const(basis)};
-    const UnitList L(a.off, a.E, 1, a.E, kUnitEval);
-    for (long long unit = blockIdx.x; unit < L.end; unit += gridDim.x) {
+    const UnitList units(a.off, a.E, 1, a.E, kUnitEval);
+    for (long long unit = blockIdx.x; unit < units.end; unit += gridDim.x) {
         Unit U;
-        if (!L.at(unit, U)) continue;
+        if (!units.at(unit, U)) continue;
         const int e = U.seg, beg = U.beg, end = U.end;
         for (int base = beg; base < end; base += kWave) {
             const int q = base + (int)threadIdx.x;
@@ -133,10 +133,10 @@ __global__ __launch_bounds__(kEvThreads) void k_eval_grp(EvArgs a, FieldPtrs F,
     __shared__ double sF[G * S];
     const BasisPtr<double> B{as_const(basis)};
     const int ns = (a.E + G - 1) / G;
-    const UnitList L(a.off, ns, G, a.E, kUnitGrp);
-    for (long long unit = blockIdx.x; unit < L.end; unit += gridDim.x) {
+    const UnitList units(a.off, ns, G, a.E, kUnitGrp);
+    for (long long unit = blockIdx.x; unit < units.end; unit += gridDim.x) {
         Unit U;
-        if (!L.at(unit, U)) continue;  // uniform
+        if (!units.at(unit, U)) continue;  // uniform
         const int e0 = U.seg * G;
         const int ne = min(G, a.E - e0);
         const int pb = U.beg, pe = U.end;
@@ -184,10 +184,10 @@ __global__ __launch_bounds__(kWave) void k_eval_mfma(EvArgs a, FieldPtrs F,
     constexpr int MBF = (N1 + S::PPB - 1) / S::PPB;  // M blocks per field (planes k)
     constexpr int NF = kEvFieldsPerPass;
     const BasisPtr<double> B{as_const(basis)};
-    const UnitList L(a.off, a.E, 1, a.E, kUnitEvalMfma);
-    for (long long unit = blockIdx.x; unit < L.end; unit += gridDim.x) {
+    const UnitList units(a.off, a.E, 1, a.E, kUnitEvalMfma);
+    for (long long unit = blockIdx.x; unit < units.end; unit += gridDim.x) {
         Unit U;
-        if (!L.at(unit, U)) continue;
+        if (!units.at(unit, U)) continue;
         const int e = U.seg, beg = U.beg, end = U.end;
         const int lane = threadIdx.x, n = lane & 15, g = lane >> 4;
         // A fragment coordinates of this lane: row -> plane p, row jj; column i

@@ -429,10 +429,10 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
     constexpr int V = N1 * N1 * N1;
     const BasisPtr<double> B{as_const(basis)};
     unsigned long long my_iters = 0;
-    const UnitList L(a.elem_off, a.E, 1, a.E, kUnitScalar);
-    for (long long u = blockIdx.x; u < L.end; u += gridDim.x) {
+    const UnitList units(a.elem_off, a.E, 1, a.E, kUnitScalar);
+    for (long long u = blockIdx.x; u < units.end; u += gridDim.x) {
         Unit U;
-        if (!L.at(u, U)) continue;
+        if (!units.at(u, U)) continue;
         const int e = U.seg;
         cptr<double> X = as_const(a.geom + (long long)e * 3 * V);
         const double he = a.esize[e];
