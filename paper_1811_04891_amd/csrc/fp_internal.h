@@ -86,6 +86,9 @@ struct fp_handle {
     float *geom32 = nullptr;   // binary32 copy (mixed precision)
     double *esize = nullptr;   // E: h_e
     double *bbox = nullptr;    // E x 6
+    double *erec = nullptr;    // E x 16 doubles (one 128-byte line per element): the
+                               // axis-aligned box (6 doubles) then the oriented box
+                               // (18 binary32 values), for the candidate tests
     float *obb = nullptr;      // E x 18 binary32: frame Q (9, row-major, rows = axes),
                                // centre (3), rotated lo (3), rotated hi (3)
     int *esess = nullptr;      // E or null

@@ -28,10 +28,10 @@ namespace fp {
 struct LocArgs {
     const double *geom;
     const double *esize;
-    const double *bbox;
     const float *obb;    // non-null: also test the oriented box (first pass)
-    const float *obb2;   // second pass: the oriented boxes, to find the candidates
-                         // the first pass dropped
+    const float *obb2;   // second pass: non-null, to find the candidates the first
+                         // pass dropped
+    const double *erec;  // per element, 16 doubles: axis-aligned box, oriented box
     int *redo;           // first pass writes 1 for tasks left without an inside
                          // candidate and with a partial candidate set, else 0
     const int *only;     // non-null (second pass): tasks with only[t] != 0
@@ -128,13 +128,13 @@ __global__ __launch_bounds__(256) void k_cand(LocArgs a)
                         xf2 > hi.z)
                         continue;
                     const int e = __float_as_int(lo.w);
-                    const double *b = a.bbox + 6 * (long long)e;
+                    const double *b = a.erec + 16 * (long long)e;  // one line: both boxes
                     if (x0 < b[0] || x0 > b[1] || x1 < b[2] || x1 > b[3] || x2 < b[4] || x2 > b[5])
                         continue;
                     if (ps >= 0 && a.esess && a.esess[e] == ps) continue;
                     if (pass == 0 || a.only) {
                         ++naabb;
-                        const float *o = (a.only ? a.obb2 : a.obb) + 18 * (long long)e;
+                        const float *o = (const float *)(b + 6);
                         const double d0 = x0 - (double)o[9], d1 = x1 - (double)o[10],
                                      d2 = x2 - (double)o[11];
                         bool in = true;
@@ -687,7 +687,7 @@ int run_findpts(fp_handle *h, const Work &w, int npts, const double *pts, const 
         LocArgs a{};
         a.geom = h->geom;
         a.esize = h->esize;
-        a.bbox = h->bbox;
+        a.erec = h->erec;
         a.delta = h->delta;
         a.esess = h->esess;
         a.cell_off = h->cell_off;

@@ -441,6 +441,21 @@ __global__ __launch_bounds__(256) void k_hash_sort(const int *__restrict__ off,
     atomicMax(maxlen, n);
 }
 
+// One 128-byte record per element for the candidate lookup: the binary64
+// axis-aligned box and the binary32 oriented box share a cache line.
+__global__ __launch_bounds__(256) void k_erec(const double *__restrict__ bbox,
+                                              const float *__restrict__ obb, int E,
+                                              double *__restrict__ erec)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    double *r = erec + 16 * (long long)e;
+    for (int i = 0; i < 6; ++i) r[i] = bbox[6 * (long long)e + i];
+    float *o = (float *)(r + 6);
+    for (int i = 0; i < 18; ++i) o[i] = obb[18 * (long long)e + i];
+    r[15] = 0.0;
+}
+
 // Per cell-list entry, the element's box in binary32 rounded outward (never
 // smaller than the binary64 box) with the element id in the spare slot: the
 // candidate lookup streams a cell's entries contiguously and tests the exact
@@ -539,7 +554,7 @@ static void release(fp_handle *h)
     void *ptrs[] = {h->d_basis, h->d_basis32, h->geom, h->geom32, h->esize, h->bbox, h->obb,
                     h->esess, h->delta, h->cell_off, h->cell_cnt, h->cell_el, h->cell_box,
                     h->work_mem, h->scan_tmp, h->stats, h->d_flag, h->d_g, h->d_binv,
-                    h->d_dnode};
+                    h->d_dnode, h->erec};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &t : h->timed) {
@@ -591,6 +606,8 @@ static int build_geometry(fp_handle *h, const double *x, const double *y, const 
     FP_HIP(hipGetLastError());
     k_obb<<<E, kWave, 2 * V * sizeof(double), s>>>(h->geom, n1, h->d_binv, h->bbox, h->esize,
                                                     h->obb);
+    FP_HIP(hipGetLastError());
+    k_erec<<<(E + 255) / 256, 256, 0, s>>>(h->bbox, h->obb, E, h->erec);
     FP_HIP(hipGetLastError());
     k_gbox<<<1, 256, 0, s>>>(h->bbox, E, h->d_g);
     FP_HIP(hipGetLastError());
@@ -754,6 +771,7 @@ extern "C" int findpts_setup(fp_handle **out, const double *x, const double *y,
     FP_HIP_H(dalloc(h, &h->esize, E));
     FP_HIP_H(dalloc(h, &h->bbox, 6 * (size_t)E));
     FP_HIP_H(dalloc(h, &h->obb, 18 * (size_t)E));
+    FP_HIP_H(dalloc(h, &h->erec, 16 * (size_t)E));
     FP_HIP_H(dalloc(h, &h->stats, 4));
     FP_HIP_H(dalloc(h, &h->d_basis, 2 * kMaxN1));
     FP_HIP_H(dalloc(h, &h->d_basis32, 2 * kMaxN1));
