@@ -193,7 +193,7 @@ def test_edge_cases(dev):
         compare_locate(om, pts.numpy(), g, om.findpts(pts.numpy()), hs, TOL)
 
 
-@pytest.mark.parametrize("N", [1, 2, 3, 4, 9, 10, 11, 15])
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 8, 9, 10, 11, 12, 13, 14, 15])
 def test_orders(dev, N):
     fp = _fp()
     _say(f"case: order N={N}")
