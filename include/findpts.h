@@ -64,7 +64,8 @@ enum fp_precision {
     FP_PREC_FP64 = 0, /* every step in binary64                              */
     FP_PREC_MIXED = 1 /* binary32 start search and early Newton iterations;
                          final Newton steps, acceptance, classification,
-                         delta and the returned residual in binary64        */
+                         delta and the returned residual in binary64; orders
+                         N >= 8 run binary64 throughout                     */
 };
 
 /*
