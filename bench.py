@@ -399,9 +399,9 @@ def main():
                     help="precision of the headline line (the other one is timed beside it)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
-              "the path shards by replicating the mesh and splitting the points, "
-              "which is not built here.", file=sys.stderr)
+        print(f"bench.py: the benchmark runs on one GPU only (asked for {args.gpus}); "
+              "several GPUs would each hold the mesh and take a share of the points, "
+              "and that sharding is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
