@@ -169,7 +169,8 @@ __global__ __launch_bounds__(kEvThreads) void k_eval_grp(EvArgs a, FieldPtrs F,
 // field's rows (n1^2 x n1) with the basis values of 16 points, one
 // v_mfma_f64_16x16x4f64 per 16 rows and 4 i-values; the field's A fragments
 // stay in registers for all points of the element.  Lane n + 16 g supplies
-// h_i(r) for i = 4 kb + g of point n, contracts its rows j = g + 4 w with
+// h_i(r) for i = 4 kb + g of point n (evaluating only its own i and j, in its
+// rotated node order), contracts its rows j = g + 4 w with
 // h_j(s) and every plane k with h_k(t), and the 4 lanes of point n add their
 // partial sums (same order in all 4: the total is bit-identical).
 constexpr int kEvFieldsPerPass = 4;
@@ -184,6 +185,8 @@ __global__ __launch_bounds__(kWave) void k_eval_mfma(EvArgs a, FieldPtrs F,
     constexpr int MBF = (N1 + S::PPB - 1) / S::PPB;  // M blocks per field (planes k)
     constexpr int NF = kEvFieldsPerPass;
     const BasisPtr<double> B{as_const(basis)};
+    LaneNodes<N1> Z;  // h_i(r), h_j(s) only for the lane's own i, j = g + 4 w
+    lane_nodes<N1>(B, threadIdx.x >> 4, Z);
     const UnitList units(a.off, a.E, 1, a.E, kUnitEvalMfma);
     for (long long unit = blockIdx.x; unit < units.end; unit += gridDim.x) {
         Unit U;
@@ -214,25 +217,11 @@ __global__ __launch_bounds__(kWave) void k_eval_mfma(EvArgs a, FieldPtrs F,
                 const int u = b0 + n;
                 const bool act = u < end;
                 const int p = a.order[act ? u : beg];
-                double hr[N1], hs[N1], ht[N1];
-                lagrange<N1>(B, a.rst[3 * (long long)p], hr);
-                lagrange<N1>(B, a.rst[3 * (long long)p + 1], hs);
+                static_assert(S::KB == S::EPP, "r and s rows use the same lane indices");
+                double hrl[S::KB], hsl[S::EPP], ht[N1];
+                lagrange_lane<N1>(Z, a.rst[3 * (long long)p], hrl);
+                lagrange_lane<N1>(Z, a.rst[3 * (long long)p + 1], hsl);
                 lagrange<N1>(B, a.rst[3 * (long long)p + 2], ht);
-                double hrl[S::KB], hsl[S::EPP];
-    #pragma unroll
-                for (int w = 0; w < S::KB; ++w) {
-                    double vr_ = 0.0, vs_ = 0.0;
-    #pragma unroll
-                    for (int gg = 0; gg < 4; ++gg) {
-                        const int i = gg + 4 * w;
-                        if (i < N1) {
-                            vr_ = (g == gg) ? hr[i] : vr_;
-                            vs_ = (g == gg) ? hs[i] : vs_;
-                        }
-                    }
-                    hrl[w] = vr_;
-                    hsl[w] = vs_;
-                }
     #pragma unroll
                 for (int f = 0; f < NF; ++f) {
                     if (f0 + f < a.nf) {

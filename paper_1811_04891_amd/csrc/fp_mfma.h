@@ -1,7 +1,7 @@
 // Matrix-core building blocks shared by the Newton and interpolation
 // kernels: the 16x16x4 MFMA in binary64 and binary32 with their register
-// layouts, the row blocking of an element's node data, and the sum over the
-// 4 lanes that share a column.
+// layouts, the row blocking of an element's node data, the basis values of
+// one lane's own rows, and the sum over the 4 lanes that share a column.
 #pragma once
 
 #include "fp_basis.h"
@@ -51,6 +51,78 @@ struct MShape {
     static constexpr int V = N1 * N1 * N1;
     static constexpr int SB = (V + 15) / 16;                      // node blocks (start scan)
 };
+
+// A lane's own node order: position p holds node (p + g) mod N1, so that the
+// indices the lane needs for its slot, i = 4 m + g, sit at the fixed positions
+// 4 m (weight 0 past the last node).  Loaded once per kernel.
+template <int N1>
+struct LaneNodes {
+    double z[N1];
+    double w[MShape<N1>::KB];
+};
+
+template <int N1>
+__device__ __forceinline__ void lane_nodes(BasisPtr<double> B, int g, LaneNodes<N1> &Z)
+{
+#pragma unroll
+    for (int p = 0; p < N1; ++p) Z.z[p] = B.z((p + g) % N1);
+#pragma unroll
+    for (int m = 0; m < MShape<N1>::KB; ++m) {
+        const int i = 4 * m + g;
+        Z.w[m] = i < N1 ? B.wb(i) : 0.0;
+    }
+}
+
+// h_i(r) and h_i'(r) for the lane's indices i = 4 m + g: the product of
+// (r - z) over the other nodes, taken in the lane's node order (prefix times
+// suffix products), so no lane computes the basis functions it does not use.
+template <int N1>
+__device__ __forceinline__ void lagrange_d_lane(const LaneNodes<N1> &Z, double r,
+                                                double (&h)[MShape<N1>::KB],
+                                                double (&d)[MShape<N1>::KB])
+{
+    double t[N1], pl[N1], dpl[N1], pr[N1], dpr[N1];
+#pragma unroll
+    for (int p = 0; p < N1; ++p) t[p] = r - Z.z[p];
+    pl[0] = 1.0;
+    dpl[0] = 0.0;
+#pragma unroll
+    for (int p = 1; p < N1; ++p) {
+        dpl[p] = dpl[p - 1] * t[p - 1] + pl[p - 1];
+        pl[p] = pl[p - 1] * t[p - 1];
+    }
+    pr[N1 - 1] = 1.0;
+    dpr[N1 - 1] = 0.0;
+#pragma unroll
+    for (int p = N1 - 2; p >= 0; --p) {
+        dpr[p] = dpr[p + 1] * t[p + 1] + pr[p + 1];
+        pr[p] = pr[p + 1] * t[p + 1];
+    }
+#pragma unroll
+    for (int m = 0; m < MShape<N1>::KB; ++m) {
+        const int p = 4 * m;
+        h[m] = Z.w[m] * (pl[p] * pr[p]);
+        d[m] = Z.w[m] * (dpl[p] * pr[p] + pl[p] * dpr[p]);
+    }
+}
+
+// h_i(r) alone for the lane's indices i = 4 m + g (as lagrange_d_lane).
+template <int N1>
+__device__ __forceinline__ void lagrange_lane(const LaneNodes<N1> &Z, double r,
+                                              double (&h)[MShape<N1>::KB])
+{
+    double t[N1], pl[N1], pr[N1];
+#pragma unroll
+    for (int p = 0; p < N1; ++p) t[p] = r - Z.z[p];
+    pl[0] = 1.0;
+#pragma unroll
+    for (int p = 1; p < N1; ++p) pl[p] = pl[p - 1] * t[p - 1];
+    pr[N1 - 1] = 1.0;
+#pragma unroll
+    for (int p = N1 - 2; p >= 0; --p) pr[p] = pr[p + 1] * t[p + 1];
+#pragma unroll
+    for (int m = 0; m < MShape<N1>::KB; ++m) h[m] = Z.w[m] * (pl[4 * m] * pr[4 * m]);
+}
 
 // Sum over the 4 lanes n + 16 g of a slot, by two lane swaps (no LDS):
 // v_permlane16_swap exchanges the odd 16-lane rows of its first operand with
