@@ -307,17 +307,28 @@ struct TRNewton {
         if (nf == 0) return true;
         // one solve for both cases (lanes of a wavefront differ in nf): J d = -F
         // when all coordinates are free, else the reduced normal equations
-        // (M J^T J M + I - M) d = -M g
+        // (M J^T J M + I - M) d = -M g; a wavefront whose lanes are all free
+        // (the usual case) skips forming the second
         double A[9], b[3], dl[3];
+        if (__all(nf == 3)) {
 #pragma unroll
-        for (int u = 0; u < 3; ++u) {
+            for (int u = 0; u < 3; ++u) {
 #pragma unroll
-            for (int v = 0; v < 3; ++v) {
-                const double jtj = fma(J[6 + u], J[6 + v], fma(J[3 + u], J[3 + v], J[u] * J[v]));
-                const double red = m[u] * m[v] * jtj + ((u == v) ? 1.0 - m[u] : 0.0);
-                A[3 * u + v] = (nf == 3) ? J[3 * u + v] : red;
+                for (int v = 0; v < 3; ++v) A[3 * u + v] = J[3 * u + v];
+                b[u] = -F[u];
             }
-            b[u] = (nf == 3) ? -F[u] : -m[u] * g[u];
+        } else {
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+#pragma unroll
+                for (int v = 0; v < 3; ++v) {
+                    const double jtj =
+                        fma(J[6 + u], J[6 + v], fma(J[3 + u], J[3 + v], J[u] * J[v]));
+                    const double red = m[u] * m[v] * jtj + ((u == v) ? 1.0 - m[u] : 0.0);
+                    A[3 * u + v] = (nf == 3) ? J[3 * u + v] : red;
+                }
+                b[u] = (nf == 3) ? -F[u] : -m[u] * g[u];
+            }
         }
         const bool ok = solve3(A, b, dl);
         if (!ok) {
