@@ -174,4 +174,43 @@ __device__ __forceinline__ T slot_sum(T v)
     return swap_add<32>(swap_add<16>(v));
 }
 
+// Lane swaps of two different binary64 values (results in the order the
+// builtins return them: first operand, second operand).
+template <int ROWS>
+__device__ __forceinline__ void swap2(double x, double y, double &xo, double &yo)
+{
+    if constexpr (ROWS == 16) {
+        const auto l = __builtin_amdgcn_permlane16_swap(lo32(x), lo32(y), false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(hi32(x), hi32(y), false, false);
+        xo = mk64(l[0], h[0]);
+        yo = mk64(l[1], h[1]);
+    } else {
+        const auto l = __builtin_amdgcn_permlane32_swap(lo32(x), lo32(y), false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(hi32(x), hi32(y), false, false);
+        xo = mk64(l[0], h[0]);
+        yo = mk64(l[1], h[1]);
+    }
+}
+
+// slot_sum of four values at once.  Swapping two different values leaves
+// the pair sums of the first in the even 16-lane rows and of the second in
+// the odd rows, so after the two reduction rounds row r holds the total of
+// value r, each formed once and in slot_sum's order; two broadcast rounds
+// then give every lane all four totals (bit-identical in the 4 lanes of a
+// slot), with half the lane swaps of four slot_sum calls.
+__device__ __forceinline__ void slot_sum4(double &a, double &b, double &c, double &d)
+{
+    double x, y;
+    swap2<16>(a, b, x, y);
+    const double sab = x + y;
+    swap2<16>(c, d, x, y);
+    const double scd = x + y;
+    swap2<32>(sab, scd, x, y);
+    const double t = x + y;  // row r: total of value r
+    double p, q;
+    swap2<32>(t, t, p, q);   // p = (a, b, a, b), q = (c, d, c, d) by rows
+    swap2<16>(p, p, a, b);
+    swap2<16>(q, q, c, d);
+}
+
 }  // namespace fp
