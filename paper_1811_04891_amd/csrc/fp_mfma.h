@@ -192,22 +192,35 @@ __device__ __forceinline__ void swap2(double x, double y, double &xo, double &yo
     }
 }
 
+template <int ROWS>
+__device__ __forceinline__ void swap2(float x, float y, float &xo, float &yo)
+{
+    const auto r = (ROWS == 16)
+                       ? __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y),
+                                                          false, false)
+                       : __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y),
+                                                          false, false);
+    xo = __uint_as_float(r[0]);
+    yo = __uint_as_float(r[1]);
+}
+
 // slot_sum of four values at once.  Swapping two different values leaves
 // the pair sums of the first in the even 16-lane rows and of the second in
 // the odd rows, so after the two reduction rounds row r holds the total of
 // value r, each formed once and in slot_sum's order; two broadcast rounds
 // then give every lane all four totals (bit-identical in the 4 lanes of a
 // slot), with half the lane swaps of four slot_sum calls.
-__device__ __forceinline__ void slot_sum4(double &a, double &b, double &c, double &d)
+template <class T>
+__device__ __forceinline__ void slot_sum4(T &a, T &b, T &c, T &d)
 {
-    double x, y;
+    T x, y;
     swap2<16>(a, b, x, y);
-    const double sab = x + y;
+    const T sab = x + y;
     swap2<16>(c, d, x, y);
-    const double scd = x + y;
+    const T scd = x + y;
     swap2<32>(sab, scd, x, y);
-    const double t = x + y;  // row r: total of value r
-    double p, q;
+    const T t = x + y;  // row r: total of value r
+    T p, q;
     swap2<32>(t, t, p, q);   // p = (a, b, a, b), q = (c, d, c, d) by rows
     swap2<16>(p, p, a, b);
     swap2<16>(q, q, c, d);
