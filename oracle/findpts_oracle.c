@@ -461,10 +461,21 @@ int or_candidates(const or_mesh *m, const double *p, int psess, int *out, int ma
  *   pred = phi - ||F + J s||^2, ared = phi - phi(r'), rho = ared / pred.
  *   Accept if rho >= 0.01.  D <- min(2D, 2) if rho > 0.75 and the radius
  *   limited the step; D <- |s|/4 if rho < 0.25.
- *   Stop: phi <= (1e-13 h_e)^2; an accepted step with |s| <= 1e-13;
- *   |s| <= 1e-15 or pred <= 0 (no progress possible); 50 iterations.
+ *   Stop: phi <= (c h_e)^2 with c = min(1e-13, tol / 10), so that a point
+ *   the tolerance accepts is never left short of it; an accepted step with
+ *   |s| <= 1e-13 (Newton converges quadratically, so the point it reaches is
+ *   at the rounding level of the map); |s| <= 1e-15 or pred <= 0 (no
+ *   progress possible); 50 iterations.
  * ------------------------------------------------------------------------- */
 #define OR_MAXIT 50
+
+/* Squared residual at which Newton stops, for tolerance tol and element
+ * size he: a tenth of the inside tolerance, at most 1e-13 h_e. */
+static double resid_stop(double tol, double he)
+{
+    double c = 0.1 * tol < 1e-13 ? 0.1 * tol : 1e-13;
+    return (c * he) * (c * he);
+}
 
 /* Solve A x = b (n <= 3) by Gaussian elimination with partial pivoting.
  * Returns 0 on success, -1 on a zero pivot or a non-finite result. */
@@ -528,12 +539,12 @@ static double resid(const or_mesh *m, int e, const double *p, const double r[3],
 static int tr_newton(const or_mesh *m, int e, const double *p, double r[3],
                      double *phi_out)
 {
-    double he = m->h[e];
+    double he = m->h[e], stop = resid_stop(m->tol, he);
     double F[3], J[9], D = 1.0;
     double phi = resid(m, e, p, r, F, J);
     int it = 0;
     while (it < OR_MAXIT) {
-        if (phi <= (1e-13 * he) * (1e-13 * he)) break;
+        if (phi <= stop) break;
         ++it;
         double g[3];
         for (int d = 0; d < 3; ++d)
@@ -1073,12 +1084,12 @@ static double resid2(const or2_mesh *m, int e, const double *p, const double r[2
 static int tr_newton2(const or2_mesh *m, int e, const double *p, double r[2],
                       double *phi_out)
 {
-    double he = m->h[e];
+    double he = m->h[e], stop = resid_stop(m->tol, he);
     double F[2], J[4], D = 1.0;
     double phi = resid2(m, e, p, r, F, J);
     int it = 0;
     while (it < OR_MAXIT) {
-        if (phi <= (1e-13 * he) * (1e-13 * he)) break;
+        if (phi <= stop) break;
         ++it;
         double g[2];
         for (int d = 0; d < 2; ++d) g[d] = J[d] * F[0] + J[2 + d] * F[1];

@@ -154,3 +154,24 @@ def test_spiral_nearest_node_start():
     assert np.any(bc == 0) and np.any(bc == 1)
     assert np.array_equal(code == 0, bc == 0)
     assert np.all(d2 >= bd * (1 - 1e-10) - 1e-30)
+
+
+@pytest.mark.parametrize("seed", [17, 19])
+def test_spiral_exact_points_inside_at_paper_tolerance(seed):
+    """Section 3.1, spiral test: random points of the element are found to a
+    tolerance of 1e-14 (relative to h_e here).  Each point is x^e(r_true),
+    built by scipy's barycentric interpolant, so the map's own rounding at
+    r_true (a few 1e-16 h_e) is the floor; Newton must not stop short of the
+    tolerance, so every point comes back inside with a residual, recomputed
+    through the map, within 1e-14 h_e."""
+    m = w.spiral_element()
+    om = oracle.OracleMesh.from_mesh(m, 1e-14)
+    _, h = om.bbox()
+    pts, rt = spiral_exact_points(m, 1000, seed)
+    code, el, rst, d2 = om.findpts(pts)
+    assert np.array_equal(np.bincount(code, minlength=3), [1000, 0, 0])
+    assert np.all(el == 0)
+    assert np.sqrt(d2).max() <= 1e-14 * h[0]
+    for i in range(0, 1000, 5):
+        assert _residual(om, 0, rst[i], pts[i]) <= 1e-14 * h[0]
+    assert np.max(np.abs(rst - rt)) <= 1e-11
