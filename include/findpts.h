@@ -109,7 +109,9 @@ FP_API int findpts_setup(fp_handle **h, const double *x, const double *y,
  * Allocates only when the new hash grid needs more room than any earlier
  * one.  Synchronises `stream` three times.  Calls on the handle that are
  * still in flight must have finished (the serving layer must not be running
- * requests on it).  Errors: FP_EINVAL (NULL, non-finite coordinates: the
+ * requests on it; requests queued on it count as in flight: if the update
+ * lengthens the longest hash-cell list, such a request later fails with
+ * FP_ESTATE instead of running in a workspace sized for the old mesh).  Errors: FP_EINVAL (NULL, non-finite coordinates: the
  * handle must then be updated again before use), FP_ESTATE, FP_ERANGE,
  * FP_EHIP.  Results afterwards equal those of a handle set up on the new
  * coordinates.
@@ -330,7 +332,9 @@ FP_API int fp_extrapolate(long long n, int order, const double *const *h_hist, d
  *                 *ticket receives a positive id.  Never blocks on the GPU.
  * fps_wait        blocks until the request completed (FP_OK or its error),
  *                 FP_EBUSY if timeout_s (>= 0; < 0 = forever) passes first.
- *                 A ticket can be waited for once.
+ *                 A ticket can be waited for once.  FP_ESTATE: the mesh was
+ *                 updated while the request was queued and its longest
+ *                 hash-cell list grew past what the workspace was sized for.
  * fps_latency     p50 / p99 latency (seconds) of the requests completed
  *                 since the last reset, and their points per second over the
  *                 span from the first submission to the last completion;

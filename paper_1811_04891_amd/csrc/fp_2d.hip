@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kWave) void k2_obb(const double *__restrict__ geom,
                                                 const double *__restrict__ binv,
                                                 const double *__restrict__ bbox,
                                                 const double *__restrict__ esize,
-                                                float *__restrict__ obb)
+                                                double tol, float *__restrict__ obb)
 {
     __shared__ double A[kMaxN1 * kMaxN1], Bc[kMaxN1 * kMaxN1], Bi[kMaxN1 * kMaxN1];
     const int e = blockIdx.x, t = threadIdx.x, V = n1 * n1;
@@ -243,7 +243,10 @@ __global__ __launch_bounds__(kWave) void k2_obb(const double *__restrict__ geom,
     amax = wave_max2(amax);
     if (t == 0) {
         const double cabs = fmax(fabs(ctr[0]), fabs(ctr[1]));
-        const double m = 1e-8 * esize[e] + 1e-14 * (amax + cabs);
+        // the axis-aligned box's margin, or the inside tolerance when that is
+        // larger (a point within tol h_e of the element may be inside; the
+        // rounded frame's rows have norm 1 to within 1e-7)
+        const double m = fmax(1e-8, (1.0 + 1e-6) * tol) * esize[e] + 1e-14 * (amax + cabs);
         float *o = obb + 10 * (long long)e;
         for (int a = 0; a < 2; ++a)
             for (int c = 0; c < 2; ++c) o[2 * a + c] = (float)Q[a][c];  // exact
@@ -485,8 +488,8 @@ constexpr int kMaxIter2 = 50;
 // equation on the free one (steepest descent if singular); scaled to the
 // trust radius (max norm) and projected.  Accept if rho >= 0.01; radius x2
 // (up to 2) if rho > 0.75 and limited, |s|/4 if rho < 0.25.  Stop: phi <=
-// (1e-13 h_e)^2, an accepted step with |s| <= 1e-13, no possible progress,
-// or 50 iterations.
+// (min(1e-13, tol/10) h_e)^2, an accepted step with |s| <= 1e-13, no
+// possible progress, or 50 iterations.
 struct TR2 {
     double r[2], F[2], J[4], phi, D, pred, ns;
     double rt[2];
@@ -600,7 +603,8 @@ __global__ __launch_bounds__(kWave) void k2_locate(Loc2 a, const double *__restr
         const int e = U.seg;
         cptr<double> X = as_const(a.geom + (long long)e * 2 * V);
         const double he = a.esize[e];
-        const double rstop = (kResidStop2 * he) * (kResidStop2 * he);
+        const double cstop = fmin(0.1 * a.tol, kResidStop2) * he;
+        const double rstop = cstop * cstop;
         const int q = U.beg + (int)threadIdx.x;
         const bool act = q < U.end;
         const int slot = act ? a.order[q] : 0;
@@ -1006,7 +1010,7 @@ extern "C" int findpts2_setup(fp2_handle **out, const double *x, const double *y
     }
     k2_bbox<<<E, kWave, 0, s>>>(h->geom, n1, h->d_binv, h->bbox, h->esize);
     FP2_HIP(hipGetLastError());
-    k2_obb<<<E, kWave, 0, s>>>(h->geom, n1, h->d_binv, h->bbox, h->esize, h->obb);
+    k2_obb<<<E, kWave, 0, s>>>(h->geom, n1, h->d_binv, h->bbox, h->esize, h->tol, h->obb);
     FP2_HIP(hipGetLastError());
     k2_gbox<<<1, 256, 0, s>>>(h->bbox, E, h->d_g);
     FP2_HIP(hipGetLastError());

@@ -29,8 +29,6 @@ struct LocArgs {
     const double *geom;
     const double *esize;
     const float *obb;    // non-null: also test the oriented box (first pass)
-    const float *obb2;   // second pass: non-null, to find the candidates the first
-                         // pass dropped
     const double *erec;  // per element, 16 doubles: axis-aligned box, oriented box
     int *redo;           // first pass writes 1 for tasks left without an inside
                          // candidate and with a partial candidate set, else 0
@@ -100,13 +98,18 @@ __global__ __launch_bounds__(256) void k_cand(LocArgs a)
                      x2 = a.pts[3 * (long long)p + 2];
         const int ps = a.psess ? a.psess[p] : -1;
         int full = a.obb ? 0 : 1;
+        bool take = true;
         if (a.only) {  // second pass: the first pass's candidates stay in their slots
             n1st = a.ncand[t] & kCountMask;
             n = n1st;
+            // a first-pass list that is already the whole set (taken without
+            // the oriented-box filter, or left intact by it) gets nothing
+            // appended: only its unsolved slots are solved again
+            take = (a.ncand[t] >> kFullBit) == 0;
         }
         const Grid &g = a.g;
         // NaN fails every comparison, so non-finite points find nothing
-        if (x0 >= g.lo[0] && x0 <= g.hi[0] && x1 >= g.lo[1] && x1 <= g.hi[1] &&
+        if (take && x0 >= g.lo[0] && x0 <= g.hi[0] && x1 >= g.lo[1] && x1 <= g.hi[1] &&
             x2 >= g.lo[2] && x2 <= g.hi[2]) {
             const long long c = cell_of(g, 0, x0) +
                                 (long long)g.nc[0] * (cell_of(g, 1, x1) +
@@ -221,10 +224,19 @@ __device__ __forceinline__ bool solve3(const double (&A)[9], const double (&b)[3
 }
 
 // Trust-region Newton constants (stop tests, radius rules).
-constexpr double kResidStop = 1e-13;  // phi <= (kResidStop h_e)^2
+constexpr double kResidStop = 1e-13;  // residual stop: at most kResidStop h_e
 constexpr double kStepStop = 1e-13;   // accepted step with |s|_inf below this
 constexpr double kStepTiny = 1e-15;   // no progress possible
 constexpr int kMaxIter = 50;
+
+// Squared residual at which Newton stops: a tenth of the inside tolerance,
+// at most kResidStop, relative to h_e (a point the tolerance accepts is never
+// left short of it).
+__device__ __forceinline__ double resid_stop(double tol, double he)
+{
+    const double c = fmin(0.1 * tol, kResidStop) * he;
+    return c * c;
+}
 
 // Projected trust-region Gauss-Newton on phi(r) = ||x(r) - x*||^2 over
 // [-1,1]^3.  A coordinate on a bound whose descent direction points outward
@@ -233,8 +245,9 @@ constexpr int kMaxIter = 50;
 // it is scaled to the trust radius (max norm) and projected on the cube.
 // rho = actual / predicted decrease; accept if rho >= 0.01; radius doubled
 // (up to 2) when rho > 0.75 and the radius limited the step, set to |s|/4
-// when rho < 0.25.  Stop: phi <= (1e-13 h_e)^2, an accepted step with
-// |s| <= 1e-13, no possible progress, or 50 iterations.
+// when rho < 0.25.  Stop: phi <= (min(1e-13, tol/10) h_e)^2, an accepted
+// step with |s| <= 1e-13 (quadratic convergence: the point it reaches is at
+// the map's rounding level), no possible progress, or 50 iterations.
 struct TRNewton {
     double r[3], F[3], J[9], phi, D, pred, ns;
     double rt[3];  // next trial point
@@ -360,6 +373,16 @@ struct TRNewton {
     }
 };
 
+// Squared distance of a node from the point as the closest-node rule defines
+// it: the squares of the x, y and z differences summed in that order, each
+// operation rounded on its own (no fused multiply-add), so that near-ties are
+// decided the same way whatever the scan's arithmetic.
+__device__ __forceinline__ double node_dist2(double t0, double t1, double t2)
+{
+#pragma clang fp contract(off)
+    return (t0 * t0 + t1 * t1) + t2 * t2;
+}
+
 // Reference coordinates of GLL node n (i + n1 (j + n1 k)).
 template <int N1>
 __device__ __forceinline__ void node_rst(BasisPtr<double> B, int n, double (&r)[3])
@@ -447,7 +470,7 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
         const int e = U.seg;
         cptr<double> X = as_const(a.geom + (long long)e * 3 * V);
         const double he = a.esize[e];
-        const double rstop = (kResidStop * he) * (kResidStop * he);
+        const double rstop = resid_stop(a.tol, he);
         const int q = U.beg + (int)threadIdx.x;
         const bool act = q < U.end;
         const int slot = act ? a.order[q] : 0;
@@ -463,8 +486,7 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
         int bq = 0;
 #pragma unroll 8
         for (int n = 0; n < V; ++n) {
-            const double dx = X[n] - xs[0], dy = X[V + n] - xs[1], dz = X[2 * V + n] - xs[2];
-            const double d = fma(dz, dz, fma(dy, dy, dx * dx));
+            const double d = node_dist2(X[n] - xs[0], X[V + n] - xs[1], X[2 * V + n] - xs[2]);
             if (d < best) {
                 best = d;
                 bq = n;
@@ -611,7 +633,20 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
         rst[3 * (long long)p + 2] = o[2];
         dist2[p] = o[3];
     }
-    if (a.obb) a.redo[t] = (c != 0 && (!full || unsolved)) ? 1 : 0;
+    if (a.obb) {
+        bool redo = c != 0 && (!full || unsolved);
+        if (c == 0 && unsolved) {
+            // a pair the binary32 phase left unsolved may be inside too: with
+            // the distance field it may belong to a session with a larger
+            // delta, without it a smaller element id wins; the second pass
+            // solves it in binary64 and selects again
+            for (int k = 0; k < n; ++k)
+                if (a.res_in[S(k)] == kUnsolved &&
+                    (a.res_dl || a.cand_el[S(k)] < a.cand_el[S(w)]))
+                    redo = true;
+        }
+        a.redo[t] = redo ? 1 : 0;
+    }
 }
 
 #define FP_DISPATCH_N1(n1, MACRO) \
@@ -756,7 +791,6 @@ int run_findpts(fp_handle *h, const Work &w, int npts, const double *pts, const 
         // second pass over the flagged tasks with the axis-aligned candidates
         // only (other tasks get no candidates and keep their result)
         a.obb = nullptr;
-        a.obb2 = h->obb;
         a.redo = nullptr;
         a.only = w.redo;
         FP_HIP(fill_int(w.elem_cnt, 0, (long long)h->E + 1, s));

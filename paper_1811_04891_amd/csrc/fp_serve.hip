@@ -86,6 +86,11 @@ struct Request {
     fps *owner = nullptr;
     long long id = 0;
     int mesh = 0, npts = 0;
+    // the mesh as sized at submit: the workspace is laid out with these, and
+    // launch refuses a handle whose candidate lists have since grown
+    fp_handle *h = nullptr;
+    int E = 0, MC = 1;
+    bool delta = false;
     const double *pts = nullptr;
     const int *psess = nullptr;
     std::vector<const double *> fields;
@@ -174,9 +179,15 @@ void on_done(void *p)
 int launch(fps *s, Request *r)
 {
     hipStream_t st = s->streams[r->slot];
-    fp_handle *h = s->meshes[r->mesh].h;
+    fp_handle *h = r->h;
+    // findpts_update between submit and admission may have lengthened the
+    // longest hash-cell list: the reserved workspace would then be too small
+    if (h->E != r->E || h->MC > r->MC || (h->delta != nullptr) != r->delta) {
+        set_error("fps: the mesh changed (findpts_update) while the request was queued");
+        return FP_ESTATE;
+    }
     Work w;
-    work_carve(w, s->arena_mem + r->off, h->E, h->MC, r->pass, h->delta != nullptr);
+    work_carve(w, s->arena_mem + r->off, r->E, r->MC, r->pass, r->delta);
     int rc = run_findpts(h, w, r->npts, r->pts, r->psess, r->code, r->el, r->rst, r->dist2, st,
                          false);
     if (rc == FP_OK && !r->fields.empty())
@@ -359,6 +370,10 @@ extern "C" int fps_submit(fps *s, int mesh_id, int npts, const double *pts,
         r->owner = s;
         r->id = s->next_id++;
         r->mesh = mesh_id;
+        r->h = m.h;
+        r->E = h->E;
+        r->MC = h->MC;
+        r->delta = h->delta != nullptr;
         r->npts = npts;
         r->pts = pts;
         r->psess = pt_session;

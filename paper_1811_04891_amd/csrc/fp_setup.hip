@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kWave) void k_bbox(const double *__restrict__ geom,
 // The rotated coordinates u = Q (x - centre) are linear in x, so the
 // Bernstein coefficients of their nodal values bound the element in that
 // frame exactly as the axis-aligned box does; any Q (orthonormal or not)
-// keeps this rigorous.  Same margin as the axis-aligned box.  The record
+// keeps this rigorous.  Margin: the axis-aligned box's, or tol h_e if larger.  The record
 // is binary32 (72 bytes, half the binary64 one, for the candidate lookup's
 // memory traffic): Q and the centre are rounded first and the bounds are
 // computed for the rounded frame, then rounded outward.
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kWave) void k_obb(const double *__restrict__ geom, 
                                                const double *__restrict__ binv,
                                                const double *__restrict__ bbox,
                                                const double *__restrict__ esize,
-                                               float *__restrict__ obb)
+                                               double tol, float *__restrict__ obb)
 {
     extern __shared__ double sh[];
     const int V = n1 * n1 * n1;
@@ -343,7 +343,10 @@ __global__ __launch_bounds__(kWave) void k_obb(const double *__restrict__ geom, 
     amax = wave_max(amax);
     if (t == 0) {
         const double cabs = fmax(fabs(ctr[0]), fmax(fabs(ctr[1]), fabs(ctr[2])));
-        const double m = 1e-8 * esize[e] + 1e-14 * (amax + cabs);
+        // the axis-aligned box's margin, or the inside tolerance when that is
+        // larger (a point within tol h_e of the element may be inside; the
+        // rounded frame's rows have norm 1 to within 1e-7)
+        const double m = fmax(1e-8, (1.0 + 1e-6) * tol) * esize[e] + 1e-14 * (amax + cabs);
         float *o = obb + 18 * (long long)e;
         for (int a = 0; a < 3; ++a)
             for (int c = 0; c < 3; ++c) o[3 * a + c] = (float)Q[a][c];  // exact
@@ -605,7 +608,7 @@ static int build_geometry(fp_handle *h, const double *x, const double *y, const 
     k_bbox<<<E, kWave, 2 * V * sizeof(double), s>>>(h->geom, n1, h->d_binv, h->bbox, h->esize);
     FP_HIP(hipGetLastError());
     k_obb<<<E, kWave, 2 * V * sizeof(double), s>>>(h->geom, n1, h->d_binv, h->bbox, h->esize,
-                                                    h->obb);
+                                                    h->tol, h->obb);
     FP_HIP(hipGetLastError());
     k_erec<<<(E + 255) / 256, 256, 0, s>>>(h->bbox, h->obb, E, h->erec);
     FP_HIP(hipGetLastError());

@@ -130,27 +130,26 @@ def test_c2_annulus_subset(dev, c2):
     _say(f"c2 subset ok {st}; pairs solved/pt {pairs / npts:.3f}, method cands/pt {cands / npts:.3f}")
 
 
-def test_c2_full_size_sampled(dev, c2):
-    """The benchmark workload (1.01M points, one pass of max_points = 2^20),
-    checked on a seeded sample of 20,000 outputs."""
+def test_c2_full_size(dev, c2):
+    """The benchmark workload at full size (1.01M points, one pass of
+    max_points = 2^20, 4 fields), every point's location and every
+    interpolated value against the oracle."""
     fp = _fp()
     mesh, pts, om = c2
-    _say("case: annulus C2 full 1.01M points, sampled parity")
-    h, g, _ = _run(fp, mesh, pts, dev, max_points=1 << 20)
-    rng = np.random.default_rng(22)
-    idx = np.sort(rng.choice(len(pts), 20_000, replace=False))
-    o = om.findpts(pts.numpy()[idx])
-    gs = tuple(a[idx] for a in g)
+    _say("case: annulus C2 full 1.01M points, 4 fields, every output")
+    md = mesh.to(dev)
+    fields, _ = w.poly_fields(md, 4, seed=2)  # built on the device, copied for the oracle
+    h, g, out = _run(fp, mesh, pts, dev, max_points=1 << 20, fields=fields)
+    o = om.findpts(pts.numpy())
     _, hs = om.bbox()
-    st = compare_locate(om, pts.numpy()[idx], gs, o, hs, TOL, check_residual_every=5)
-    # whole-output properties at full size
-    gc, ge, gr, gd = g
-    assert np.all((gc >= 0) & (gc <= 2))
-    assert np.all((ge >= -1) & (ge < mesh.E))
-    assert np.all(np.abs(gr) <= 1.0)
-    assert np.all((gc == 2) == np.isinf(gd))
-    assert np.sum(gc == 0) > 0.985 * len(pts)
-    _say(f"c2 full sampled ok {st}")
+    st = compare_locate(om, pts.numpy(), g, o, hs, TOL, check_residual_every=50)
+    assert st["border"] > 0 and st["notfound"] > 0
+    hf = [f.cpu().numpy() for f in fields]
+    compare_eval(out, om.eval(g[0], g[1], g[2], hf), hf)
+    pairs, _, npts, cands = fp.findpts_stats(h)
+    assert cands == om.last_stats[0] and npts == len(pts)
+    _say(f"c2 full ok {st}")
+    h.free()
 
 
 def test_chunked_equals_single_pass(dev):
@@ -244,11 +243,10 @@ def test_spiral_n15(dev):
     are all found with r_true recovered, points between the turns match the
     oracle (both start Newton at the closest GLL node, so both settle in the
     same local minimum), and evaluating the coordinate fields at the returned
-    (el, r) gives the points back.  At tol = 1e-14 the inside test sits at the
-    rounding floor of the binary64 map (|x| up to 4.6, h = 6.25), so the two
-    sides may call an exact point inside or border differently; there the
-    checks are r_true recovered, a distance at that floor, and every GPU
-    inside answer passing the oracle's residual to 1.5 tol h."""
+    (el, r) gives the points back.  At the paper's tolerance of 1e-14 (h_e
+    relative) every exact point is found inside on both sides, with full
+    parity and the GPU's residual, recomputed by the oracle's map, within
+    tol h_e."""
     fp = _fp()
     from helpers import spiral_exact_points
     _say("case: spiral element N=15, 1000 exact + 1000 box + 16 far points")
@@ -279,13 +277,13 @@ def test_spiral_n15(dev):
     om14 = oracle.OracleMesh.from_mesh(mesh, tol)
     oc = om14.findpts(ex)[0]
     gc, ge, gr, gd = g14
-    assert np.all(ge == 0) and np.all(gc <= 1)
+    assert np.array_equal(np.bincount(oc, minlength=3), [1000, 0, 0])
+    assert np.array_equal(np.bincount(gc, minlength=3), [1000, 0, 0])
+    assert np.all(ge == 0)
     assert np.max(np.abs(gr - rt)) <= 1e-11
-    assert np.sqrt(gd).max() <= 1e-13 * hs[0]
-    for i in np.nonzero(gc == 0)[0]:
-        x, _ = om14.map(0, gr[i])
-        assert np.linalg.norm(x - ex[i]) <= 1.5 * tol * hs[0], i
-    _say(f"spiral tol 1e-14: inside gpu {int(np.sum(gc == 0))} oracle {int(np.sum(oc == 0))} of 1000")
+    assert np.sqrt(gd).max() <= tol * hs[0]
+    st14 = compare_locate(om14, ex, g14, om14.findpts(ex), hs, tol)
+    _say(f"spiral tol 1e-14: {st14}")
 
 
 def test_eval_reference_polynomials(dev):
@@ -370,7 +368,8 @@ def test_c5_large_box_full_size_sampled(dev):
     _say("case: large box C5, 200,000 elements, 2e7 points, sampled parity")
     mesh = w.big_box_c5()
     pts = w.queries_c5()
-    h, g, _ = _run(fp, mesh, pts, dev, max_points=1 << 20)
+    fields, _ = w.poly_fields(mesh.to(dev), 5, seed=5)  # on the device
+    h, g, out = _run(fp, mesh, pts, dev, max_points=1 << 20, fields=fields)
     _invariants(g, mesh.E)
     rng = np.random.default_rng(55)
     idx = np.sort(rng.choice(len(pts), 20_000, replace=False))
@@ -378,6 +377,10 @@ def test_c5_large_box_full_size_sampled(dev):
     _, hs = om.bbox()
     st = _sampled(om, pts.numpy(), g, idx, hs)
     assert st["inside"] > 0.8 * len(idx) and st["border"] + st["notfound"] > 0
+    hf = [f.cpu().numpy() for f in fields]
+    compare_eval(out[:, idx], om.eval(g[0][idx], g[1][idx], g[2][idx], hf), hf)
+    assert np.array_equal(np.isnan(out[0]), g[0] == 2)
+    del hf
     _say(f"c5 fp64 ok {st}")
     fp.findpts_set_precision(h, fp.FP_PREC_MIXED)
     code, el, rst, d2 = fp.findpts(h, pts.to(dev))
@@ -400,7 +403,8 @@ def test_c3_interface_faces_full_size_sampled(dev):
     _say("case: two sessions C3, 1.2e6 interface-face points, sampled parity")
     mesh = w.overlap_c3()
     pts, tags = w.queries_c3(n=1_200_000)
-    h, g, _ = _run(fp, mesh, pts, dev, max_points=1 << 21, psess=tags)
+    fields, _ = w.poly_fields(mesh.to(dev), 5, seed=3)  # on the device
+    h, g, out = _run(fp, mesh, pts, dev, max_points=1 << 21, psess=tags, fields=fields)
     _invariants(g, mesh.E)
     sess = mesh.session.numpy()
     found = g[0] != 2
@@ -410,6 +414,8 @@ def test_c3_interface_faces_full_size_sampled(dev):
     om = oracle.OracleMesh.from_mesh(mesh, TOL)
     _, hs = om.bbox()
     st = _sampled(om, pts.numpy(), g, idx, hs, psess=tags.numpy())
+    hf = [f.cpu().numpy() for f in fields]
+    compare_eval(out[:, idx], om.eval(g[0][idx], g[1][idx], g[2][idx], hf), hf)
     _say(f"c3 full ok {st}")
     h.free()
 
