@@ -151,6 +151,23 @@ FP_API int findpts_eval(fp_handle *h, int npts, const int *code, const int *el,
                  const double *rst, int nfields,
                  const double *const *h_fields, double *out, void *stream);
 
+/*
+ * findpts_eval_noalloc -- findpts_eval for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same interpolation, bit-identical
+ * results, but the point grouping uses a file-scope device array of 32 MiB
+ * per GPU (held by the library until the process ends) instead of the
+ * handle's workspace.  Calls no hipMalloc/hipFree and creates no events.
+ * Arguments as findpts_eval; any npts (it runs in passes).  FP_ERANGE if the
+ * mesh has more elements than the array's per-element counters allow (about
+ * 4.19 million).  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, other threads, other handles) race and
+ * must be serialised by the caller; each call clears what it uses.
+ */
+FP_API int findpts_eval_noalloc(fp_handle *h, int npts, const int *code, const int *el,
+                                const double *rst, int nfields,
+                                const double *const *h_fields, double *out, void *stream);
+
 /* Switch precision (fp_precision) for later calls; FP_EINVAL if unknown.
  * Mixed precision needs no new allocation: the binary32 geometry copy is
  * built at setup. */

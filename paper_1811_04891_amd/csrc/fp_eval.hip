@@ -3,7 +3,9 @@
 // with a counting sort so that one 64-lane wavefront reads an element's field
 // values once (scalar loads) for a run of its points (a work unit; an element
 // with many points is spread over several units).
+#include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "fp_basis.h"
 #include "fp_internal.h"
@@ -356,9 +358,114 @@ int run_eval(fp_handle *h, const Work &w, int npts, const int *code, const int *
     return FP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Interpolation without any allocation: the grouping arrays (element
+// counters and offsets, the scan's block sums, each point's rank and the
+// element-ordered point list) live in one file-scope device array.  Each
+// device holds its own copy at its own address, found once per device with
+// hipGetSymbolAddress; the host never passes the array's name to a kernel.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(32) << 20;  // 32 MiB per device
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[kScratchDevices] = {};
+
+// Address of the current device's scratch array (resolved on first use,
+// with that device current).
+int scratch_ptr(int dev, char **p)
+{
+    if (dev < 0 || dev >= kScratchDevices) {
+        set_error("scratch: device ordinal out of range");
+        return FP_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *q = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !q) return hip_fail(e == hipSuccess ? hipErrorUnknown : e,
+                                                   "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = (char *)q;
+    }
+    *p = g_scratch_ptr[dev];
+    return FP_OK;
+}
+
+// Eval-only workspace carved from the scratch array: counters and offsets
+// of E + 1 elements and the scan's block sums, then two arrays of M points
+// per pass, M as large as the array allows.  Returns false when E leaves no
+// room for a pass of kScratchMinPass points.
+constexpr int kScratchMinPass = 1024;
+
+static size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+static bool scratch_carve(char *base, int E, int npts, Work &w)
+{
+    const size_t e1 = (size_t)E + 1;
+    const size_t fixed = 2 * round256(e1 * sizeof(int)) +
+                         round256((size_t)scan_tmp_size((long long)E + 1) * sizeof(int));
+    if (fixed >= kScratchBytes) return false;
+    const size_t per = (kScratchBytes - fixed) / 2 / 256 * 256 / sizeof(int);  // ints per array
+    if (per < (size_t)kScratchMinPass) return false;
+    const int M = (int)std::min<size_t>(per, (size_t)std::max(npts, 1));
+    char *q = base;
+    w = Work{};
+    w.M = M;
+    w.E = E;
+    w.ev_cnt = (int *)q;
+    q += round256(e1 * sizeof(int));
+    w.ev_off = (int *)q;
+    q += round256(e1 * sizeof(int));
+    w.scan_tmp = (int *)q;
+    q += round256((size_t)scan_tmp_size((long long)E + 1) * sizeof(int));
+    w.ev_pos = (int *)q;
+    q += per * sizeof(int);
+    w.ev_order = (int *)q;
+    return true;
+}
+
 }  // namespace fp
 
 using namespace fp;
+
+extern "C" int findpts_eval_noalloc(fp_handle *h, int npts, const int *code, const int *el,
+                                    const double *rst, int nfields,
+                                    const double *const *h_fields, double *out, void *stream)
+{
+    if (!h) {
+        set_error("findpts_eval_noalloc: NULL handle");
+        return FP_EINVAL;
+    }
+    if (npts < 0 || nfields < 1) {
+        set_error("findpts_eval_noalloc: npts < 0 or nfields < 1");
+        return FP_EINVAL;
+    }
+    if (npts == 0) return FP_OK;
+    if (!code || !el || !rst || !h_fields || !out) {
+        set_error("findpts_eval_noalloc: NULL argument");
+        return FP_EINVAL;
+    }
+    for (int f = 0; f < nfields; ++f)
+        if (!h_fields[f]) {
+            set_error("findpts_eval_noalloc: NULL field pointer");
+            return FP_EINVAL;
+        }
+    int dev = 0;
+    FP_HIP(hipGetDevice(&dev));
+    if (dev != h->device) FP_HIP(hipSetDevice(h->device));
+    char *base = nullptr;
+    const int rc = scratch_ptr(h->device, &base);
+    if (rc != FP_OK) return rc;
+    Work w;
+    if (!scratch_carve(base, h->E, npts, w)) {
+        set_error("findpts_eval_noalloc: the mesh has too many elements for the 32 MiB scratch "
+                  "array (at most about 4 million)");
+        return FP_ERANGE;
+    }
+    return run_eval(h, w, npts, code, el, rst, nfields, h_fields, out, (hipStream_t)stream,
+                    false);
+}
 
 extern "C" int findpts_eval(fp_handle *h, int npts, const int *code, const int *el,
                             const double *rst, int nfields, const double *const *h_fields,

@@ -136,6 +136,9 @@ namespace fp {
 
 void set_error(const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
+// Device address of the interpolation scratch array of device dev (resolved
+// once per device, with dev current); FP_OK or an error code.
+int scratch_ptr(int dev, char **p);
 hipEvent_t pool_event(fp_handle *h);
 
 #define FP_HIP(call)                                         \

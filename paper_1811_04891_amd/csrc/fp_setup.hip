@@ -754,6 +754,16 @@ extern "C" int findpts_setup(fp_handle **out, const double *x, const double *y,
         set_error("findpts_setup: no HIP device");
         return FP_EHIP;
     }
+    {
+        // resolve this device's interpolation scratch array at set-up, so
+        // that findpts_eval_noalloc never resolves it inside a capture
+        char *sp = nullptr;
+        const int rc = scratch_ptr(h->device, &sp);
+        if (rc != FP_OK) {
+            delete h;
+            return rc;
+        }
+    }
     h->E = E;
     h->N = N;
     h->n1 = (int)n1;

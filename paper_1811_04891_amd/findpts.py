@@ -23,7 +23,8 @@ FP_INSIDE, FP_BORDER, FP_NOT_FOUND = 0, 1, 2
 FP_PREC_FP64, FP_PREC_MIXED = 0, 1
 
 # Every symbol the C ABI exports (checked against include/findpts.h by tests).
-SYMBOLS = ("findpts_setup", "findpts_update", "findpts", "findpts_eval", "findpts_set_precision",
+SYMBOLS = ("findpts_setup", "findpts_update", "findpts", "findpts_eval", "findpts_eval_noalloc",
+           "findpts_set_precision",
            "findpts_stats", "findpts_timing", "findpts_timing_read",
            "findpts_get_bbox", "findpts_get_hash", "findpts_get_cells",
            "findpts_footprint", "findpts_free", "fp_last_error", "fp_copy",
@@ -60,6 +61,7 @@ def lib():
     L.findpts_update.argtypes = [vp, vp, vp, vp, vp, vp]
     L.findpts.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, vp]
     L.findpts_eval.argtypes = [vp, C.c_int, vp, vp, vp, C.c_int, C.POINTER(vp), vp, vp]
+    L.findpts_eval_noalloc.argtypes = [vp, C.c_int, vp, vp, vp, C.c_int, C.POINTER(vp), vp, vp]
     L.findpts_set_precision.argtypes = [vp, C.c_int]
     L.findpts_stats.argtypes = [vp, llp, C.c_int]
     L.findpts_timing.argtypes = [vp, C.c_int]
@@ -205,6 +207,24 @@ def findpts_eval(h: Handle, code: torch.Tensor, el: torch.Tensor, rst: torch.Ten
                             _ptr(rst, torch.float64, "rst", 3 * n), nf, arr,
                             _ptr(out, torch.float64, "out", nf * n), _stream(stream))
     _check(rc, "findpts_eval")
+    return out
+
+
+def findpts_eval_noalloc(h: Handle, code: torch.Tensor, el: torch.Tensor, rst: torch.Tensor,
+                         fields: Sequence[torch.Tensor], out: torch.Tensor,
+                         stream=None) -> torch.Tensor:
+    """findpts_eval through the entry point that allocates nothing: the
+    caller passes out (nfields x npts float64); the grouping arrays live in
+    the library's per-GPU scratch array (calls on one GPU must not overlap)."""
+    n = code.numel()
+    nf = len(fields)
+    arr = (C.c_void_p * max(nf, 1))(*[_ptr(f, torch.float64, f"fields[{i}]", h.E * h.V)
+                                       for i, f in enumerate(fields)])
+    rc = lib().findpts_eval_noalloc(h.ptr, n, _ptr(code, torch.int32, "code", n),
+                                    _ptr(el, torch.int32, "el", n),
+                                    _ptr(rst, torch.float64, "rst", 3 * n), nf, arr,
+                                    _ptr(out, torch.float64, "out", nf * n), _stream(stream))
+    _check(rc, "findpts_eval_noalloc")
     return out
 
 

@@ -57,6 +57,7 @@ def test_calls_on_null_handle():
     L = fp.lib()
     assert L.findpts(None, 1, None, None, None, None, None, None, None) == fp.FP_EINVAL
     assert L.findpts_eval(None, 1, None, None, None, 1, None, None, None) == fp.FP_EINVAL
+    assert L.findpts_eval_noalloc(None, 1, None, None, None, 1, None, None, None) == fp.FP_EINVAL
     assert L.findpts_set_precision(None, 0) == fp.FP_EINVAL
     assert L.findpts_free(None) == fp.FP_OK
     assert L.fp_copy(C.c_void_p(8), C.c_void_p(16), 16, None) == fp.FP_EINVAL
