@@ -1,25 +1,29 @@
 """Benchmark: points located + interpolated per second on one MI355X.
 
-Workload (one step = findpts + findpts_eval of every query point): the
-cylinder-in-box annulus, 16,384 curved hexahedra of order 7 (64 azimuthal x
-16 radial x 16 axial, rho in [0.5, 1], z in [0, 1], nodes at exact polar
-positions), 1,010,000 query points (1e6 area-uniform in the annulus plus 1 %
-outside it), 4 float64 fields given as random polynomials of total degree 7.
-All inputs are synthetic, seeded, and resident in HBM before timing starts.
-Both precisions are timed; --precision picks the headline one.
+Headline workload (one step = findpts + findpts_eval of every query point):
+the large box, 200,000 sine-perturbed hexahedra of order 7 (100 x 50 x 40
+on [0,2] x [0,1] x [0,0.8], 68.6 M unique GLL points), 2e7 query points
+clustered near 8 random interior spheres (normal offsets N(0, 0.01^2), in
+random order; points outside the domain kept), 5 float64 fields given as
+random polynomials of total degree 7, in passes of 5e6 points.  All inputs
+are synthetic, seeded, built on the device and resident in HBM before timing
+starts.  Both precisions are timed; --precision picks the headline one.
 
 Prints one JSON line.  Besides the throughput it reports:
-  roofline      the Newton (locate) kernel, FP64: algorithmic flops per launch
-                / its mean duration (HIP events recorded by the library on the
-                launch stream) vs 78.6 TFLOP/s; HBM traffic from the committed
+  roofline      the first-pass Newton (locate) kernel of the headline
+                precision: algorithmic flops per launch / its mean duration
+                (HIP events the library records on the launch stream) vs
+                78.6 TFLOP/s; HBM bytes per launch from the committed
                 hardware-counter summary when it was taken on this source
   cpu_baseline  the CPU oracle timed on a bounded sample of the same points
-  spiral        the N = 15 spiral element at tol 1e-14: 1000 points (the
-                paper's robustness case) and 1e6 points
-  twod          the two-dimensional path on a 16,384-element ring
-  serving       a stream of requests on 16 resident meshes through the
-                serving layer: saturated throughput and p50/p99 latency at
-                0.5, 0.8 and 0.95 of the saturated request rate
+  legs          the other workloads: the annulus (16,384 elements, 1.01e6
+                points, 4 fields) in both precisions plus a moving-mesh
+                re-setup, the unit cube (64 elements, 1e4 points, 1 field),
+                the two overlapping sessions with 1.2e6 interface-face points
+                (4 fields) in both precisions, the N = 15 spiral at tol 1e-14,
+                the Schwarz interface exchange, the two-dimensional ring, and
+                a serving stream on 16 resident meshes (saturated throughput
+                and p50/p99 latency at 0.5, 0.8 and 0.95 of it)
 """
 import argparse
 import hashlib
@@ -33,7 +37,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6
-PROFILE_PMC = os.path.join(ROOT, "profiles", "locate_annulus_c2_pmc.txt")
+PEAK_HBM_GBPS = 8000.0
 
 
 def locate_flops_per_point(N, c, K):
@@ -59,25 +63,26 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per locate launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
-    if not os.path.exists(PROFILE_PMC):
+def read_profile(name):
+    """Key: value pairs of a committed rocprofv3 counter summary under
+    profiles/, if it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(PROFILE_PMC):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_hash") != kernel_source_hash():
         return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    return vals
 
 
-def cpu_baseline(mesh, pts, fields, target_s=10.0):
+def cpu_baseline(mesh, pts, fields, desc, target_s=10.0, psess=None):
+    """The oracle (plain C double, OpenMP over points) on the first n points
+    of the workload, n sized from a probe so that the timed call takes about
+    target_s on all host threads; also one core on 20,000 of them."""
     import numpy as np
 
     import oracle
@@ -85,29 +90,33 @@ def cpu_baseline(mesh, pts, fields, target_s=10.0):
     nthreads = len(os.sched_getaffinity(0))
     cores = oracle.threads(nthreads)
     p = pts.cpu().numpy()
-    # size the sample from a probe large enough to keep every thread busy
+    ps = None if psess is None else psess.cpu().numpy()
     probe_n = min(len(p), 50_000)
     t = time.perf_counter()
-    om.findpts(p[:probe_n], nthreads=nthreads)
+    om.findpts(p[:probe_n], None if ps is None else ps[:probe_n], nthreads=nthreads)
     dt = time.perf_counter() - t
     n = int(min(len(p), max(probe_n, probe_n * target_s / max(dt, 1e-3))))
     sample = p[:n]
+    sps = None if ps is None else ps[:n]
     hf = [f.cpu().numpy() for f in fields]
     t = time.perf_counter()
-    code, el, rst, _ = om.findpts(sample, nthreads=nthreads)
+    code, el, rst, _ = om.findpts(sample, sps, nthreads=nthreads)
     om.eval(code, el, rst, hf, nthreads=nthreads)
     t_loc = time.perf_counter() - t
     c = om.last_stats[0] / n
     K = om.last_stats[1] / max(om.last_stats[0], 1)
-    # one core on a 20,000-point slice of the same sample
     n1 = min(n, 20_000)
     t = time.perf_counter()
-    c1, e1, r1, _ = om.findpts(sample[:n1], nthreads=1)
+    c1, e1, r1, _ = om.findpts(sample[:n1], None if sps is None else sps[:n1], nthreads=1)
     om.eval(c1, e1, r1, hf, nthreads=1)
     t1 = time.perf_counter() - t
-    oracle.threads(nthreads)  # restore the thread count for later oracle calls
-    return {"n": n, "seconds": t_loc, "cores": cores, "c": c, "K": K, "om": om,
-            "sample_code": code, "one_core": n1 / t1}
+    oracle.threads(nthreads)
+    return {"value": n / t_loc, "unit": "points/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {n} of the {len(p)} query points of {desc}, findpts + "
+                      f"findpts_eval of the {len(fields)} fields (plain C double, OpenMP), "
+                      f"{t_loc:.1f} s",
+            "method_candidates_per_point": c, "method_newton_iters_per_candidate": K,
+            "one_core_points_per_s": n1 / t1}
 
 
 def serving_bench(fp, w, dev, precision, n_req, n_warm, slots=4, seed=40):
@@ -377,13 +386,123 @@ def twod_bench(fp, w, dev, steps=20, warmup=3, nfields=4):
             "findpts2_tflops": flops / (ms_loc / 1e3) / 1e12, "codes": codes}
 
 
+
+
+def run_workload(fp, dev, mesh, pts, fields, steps, warmup, max_points, precisions,
+                 psess=None, tol=1e-12):
+    """findpts + findpts_eval of every point per step, for each precision in
+    turn on one handle.  Per precision: ms per step (HIP events around the
+    steps on the launch stream), the library's per-kernel timings, device
+    counters, and the results of the last step."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+    P = pts.shape[0]
+    nf = len(fields)
+    t0 = time.perf_counter()
+    h = fp.findpts_setup(mesh.x, mesh.y, mesh.z, mesh.N, tol=tol, elem_session=mesh.session,
+                         delta=mesh.delta, max_points=max_points)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    code = torch.empty(P, dtype=torch.int32, device=dev)
+    el = torch.empty(P, dtype=torch.int32, device=dev)
+    rst = torch.empty((P, 3), dtype=torch.float64, device=dev)
+    d2 = torch.empty(P, dtype=torch.float64, device=dev)
+    out = torch.empty((nf, P), dtype=torch.float64, device=dev) if nf else None
+
+    def step():
+        fp.findpts(h, pts, psess, code, el, rst, d2)
+        if nf:
+            fp.findpts_eval(h, code, el, rst, fields, out)
+
+    res = {}
+    for prec in precisions:
+        fp.findpts_set_precision(h, prec)
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        fp.findpts_stats(h, reset=True)
+        fp.findpts_timing(h, True)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(steps):
+            step()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / steps
+        fp.findpts_timing(h, False)
+        tim = fp.findpts_timing_read(h)
+        counts = fp.findpts_stats(h, first_pass=True)
+        res[prec] = {"ms": ms, "tim": tim, "counts": counts, "steps": steps,
+                     "res": (code.cpu().numpy(), el.cpu().numpy(), rst.cpu().numpy(),
+                             d2.cpu().numpy()),
+                     "out": None if out is None else out.cpu().numpy()}
+        print(f"# {mesh.name} {'mixed' if prec else 'fp64'}: {ms:.3f} ms/step, "
+              f"{P / ms * 1e3:.4g} points/s; kernels {tim}", file=sys.stderr, flush=True)
+    return h, setup_s, res, step
+
+
+def summarize(N, P, nf, r):
+    """Throughput, kernel breakdown and the first-pass Newton kernel's
+    achieved binary64 rate for one precision of one workload."""
+    import numpy as np
+
+    tim = r["tim"]
+    pairs, iters, located, cands, pairs1, iters1 = r["counts"]
+    per = lambda k: tim[k][0] / max(tim[k][1], 1)
+    launches = max(tim["locate_kernel"][1], 1)
+    c1 = pairs1 / max(located, 1)
+    K1 = iters1 / max(pairs1, 1)
+    flops_launch = located / launches * locate_flops_per_point(N, c1, K1)
+    return {
+        "value": P / (r["ms"] / 1e3), "unit": "points/s", "ms_per_step": r["ms"],
+        "breakdown_ms": {"locate_kernel": per("locate_kernel"),
+                         "locate_kernel_2nd_pass": per("locate_kernel_2"),
+                         "eval_kernel": per("eval_kernel"),
+                         "findpts": per("findpts"), "findpts_eval": per("findpts_eval"),
+                         "locate_launches_per_step": launches / r["steps"]},
+        "pairs_per_point": pairs / max(located, 1),
+        "first_pass_pairs_per_point": c1,
+        "newton_iters_per_pair": iters / max(pairs, 1),
+        "first_pass_newton_iters_per_pair": K1,
+        "method_candidates_per_point": cands / max(located, 1),
+        "locate_alg_flops_per_launch": flops_launch,
+        "locate_tflops": flops_launch / (per("locate_kernel") / 1e3) / 1e12,
+        "eval_alg_flops_per_step": P * eval_flops_per_point(N, nf),
+        "codes": np.bincount(r["res"][0], minlength=3).tolist(),
+    }
+
+
+def agreement(r64, rmx, nf):
+    """Mixed precision against binary64 on the same workload: codes,
+    elements (face ties), |dr| and the interpolated values."""
+    import numpy as np
+
+    c64, e64, g64, _ = r64["res"]
+    cmx, emx, gmx, _ = rmx["res"]
+    same = (e64 == emx) & (c64 == cmx)
+    ins = same & (c64 == 0)
+    rec = {"codes_equal": bool(np.array_equal(c64, cmx)),
+           "elements_differ": int(np.sum(e64 != emx)),
+           "max_abs_dr": float(np.max(np.abs(g64[ins] - gmx[ins]))) if np.any(ins) else 0.0}
+    if nf and r64["out"] is not None:
+        o64, omx = r64["out"][:, ins], rmx["out"][:, ins]
+        scale = np.maximum(np.max(np.abs(o64), axis=1), 1e-300)[:, None]
+        err = np.abs(omx - o64) / scale
+        rec["field_err_rel_max"] = float(err.max()) if err.size else 0.0
+        rec["field_err_rel_median"] = float(np.median(err)) if err.size else 0.0
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--points", type=int, default=1_000_000,
-                    help="in-annulus points (1 %% more are placed outside)")
+    ap.add_argument("--points", type=int, default=20_000_000,
+                    help="query points of the headline workload")
+    ap.add_argument("--max-points", type=int, default=5_000_000,
+                    help="points per findpts pass (the handle's workspace)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -393,8 +512,7 @@ def main():
                     help="measured requests of the serving stream (0 = skip it)")
     ap.add_argument("--serving-warmup", type=int, default=50)
     ap.add_argument("--headline-only", action="store_true",
-                    help="skip the moving-mesh, spiral and Schwarz-exchange sections (for "
-                         "profiler runs of the headline kernels)")
+                    help="time only the headline workload (for profiler runs)")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="precision of the headline line (the other one is timed beside it)")
     args = ap.parse_args()
@@ -411,175 +529,140 @@ def main():
     from paper_1811_04891_amd import findpts as fp
 
     dev = torch.device("cuda:0")
-    mesh_cpu = w.annulus_c2()
-    mesh = mesh_cpu.to(dev)
-    pts = w.queries_c2(n_in=args.points).to(dev)
-    P = pts.shape[0]
-    fields, _ = w.poly_fields(mesh, 4, degree=7, seed=2)
-    N = mesh.N
-    print(f"# setup: E={mesh.E} N={N} points={P} fields=4", file=sys.stderr, flush=True)
-
     stream = torch.cuda.current_stream()
-    t0 = time.perf_counter()
-    h = fp.findpts_setup(mesh.x, mesh.y, mesh.z, N, tol=1e-12, max_points=1 << 20)
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    code = torch.empty(P, dtype=torch.int32, device=dev)
-    el = torch.empty(P, dtype=torch.int32, device=dev)
-    rst = torch.empty((P, 3), dtype=torch.float64, device=dev)
-    d2 = torch.empty(P, dtype=torch.float64, device=dev)
-    out = torch.empty((4, P), dtype=torch.float64, device=dev)
-
-    def step():
-        fp.findpts(h, pts, None, code, el, rst, d2)
-        fp.findpts_eval(h, code, el, rst, fields, out)
-
-    def timed(prec):
-        fp.findpts_set_precision(h, prec)
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        fp.findpts_stats(h, reset=True)
-        fp.findpts_timing(h, True)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        for _ in range(args.steps):
-            step()
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        total_ms = ev0.elapsed_time(ev1)
-        fp.findpts_timing(h, False)
-        tim = fp.findpts_timing_read(h)
-        counts = fp.findpts_stats(h)
-        ms = total_ms / args.steps
-        res = (code.cpu().numpy(), el.cpu().numpy(), rst.cpu().numpy(), d2.cpu().numpy())
-        print(f"# {'mixed' if prec else 'fp64'}: {ms:.3f} ms/step, {P / ms * 1e3:.4g} points/s; "
-              f"kernels {tim}", file=sys.stderr, flush=True)
-        return ms, tim, counts, res
-
     head = fp.FP_PREC_MIXED if args.precision == "mixed" else fp.FP_PREC_FP64
     other = fp.FP_PREC_FP64 if head == fp.FP_PREC_MIXED else fp.FP_PREC_MIXED
-    ms_o, tim_o, counts_o, res_o = timed(other)
-    ms_per_step, tim, (pairs, iters, located, cands), res_h = timed(head)
-    value = P / (ms_per_step / 1e3)
-    codes = np.bincount(res_h[0], minlength=3)
-    # agreement of the two precisions on this workload
-    res64, resmx = (res_h, res_o) if head == fp.FP_PREC_FP64 else (res_o, res_h)
-    same_el = res64[1] == resmx[1]
-    agree = {
-        "codes_equal": bool(np.array_equal(res64[0], resmx[0])),
-        "elements_differ": int(np.sum(~same_el)),
-        "max_abs_dr": float(np.max(np.abs(res64[2][same_el] - resmx[2][same_el]))),
-    }
+    pname = {fp.FP_PREC_FP64: "fp64", fp.FP_PREC_MIXED: "mixed"}
 
-    cb = None
-    if not args.no_cpu_baseline:
-        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        cb = cpu_baseline(mesh_cpu, pts, fields, args.cpu_seconds)
-    # algorithmic flops of the launches timed: the (point, element) pairs the
-    # kernel solves and their Newton iterations, as counted on the device
-    # (the method's own candidate count, measured by the oracle, is larger:
-    # the oriented-box filter removes most non-owner candidates)
-    c_gpu = pairs / max(located, 1)
-    K_gpu = iters / max(pairs, 1)
-    c_alg, K_alg = c_gpu, K_gpu
-    loc_ms = tim["locate_kernel"][0] / max(tim["locate_kernel"][1], 1)
-    ev_ms = tim["eval_kernel"][0] / max(tim["eval_kernel"][1], 1)
-    alg_flops = P * locate_flops_per_point(N, c_alg, K_alg)
-    achieved = alg_flops / (loc_ms / 1e3) / 1e12
-    traffic = read_traffic()
+    # ---- headline: the large box ------------------------------------------
+    mesh = w.big_box_c5(device=dev)
+    pts = w.queries_c5(n=args.points, device=dev)
+    fields, _ = w.poly_fields(mesh, 5, degree=7, seed=5)
+    P, N, nf = pts.shape[0], mesh.N, len(fields)
+    torch.cuda.synchronize()
+    print(f"# setup: E={mesh.E} N={N} points={P} fields={nf}", file=sys.stderr, flush=True)
+    h, setup_s, res, _ = run_workload(fp, dev, mesh, pts, fields, args.steps, args.warmup,
+                                      args.max_points, (other, head))
+    sh, so = summarize(N, P, nf, res[head]), summarize(N, P, nf, res[other])
+    h.free()
+    prof = read_profile(f"locate_big_box_c5_{pname[head]}_pmc.txt")
+    traffic = float(prof["hbm_bytes_per_launch"]) if prof else None
     rec = {
         "metric": "points located+interpolated/sec, FP64 vs mixed; p50/p99 request latency",
-        "value": value,
+        "value": sh["value"],
         "unit": "points/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": sh["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if head == fp.FP_PREC_FP64 else "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": "annulus_c2: 16,384 curved hexes N=7 (64x16x16, exact arcs), "
-                        f"{P} query points (1% outside), 4 f64 fields; findpts+findpts_eval, "
-                        f"{args.precision}",
-            "E": mesh.E, "N": N, "points": P, "fields": 4, "precision": args.precision,
-            "parallelism": "single GPU",
+            "workload": f"big_box_c5: 200,000 curved hexes N=7 (100x50x40, sine-perturbed), "
+                        f"{P} query points near 8 random spheres (random order), {nf} f64 "
+                        f"fields; findpts+findpts_eval, {args.precision}",
+            "E": mesh.E, "N": N, "points": P, "fields": nf, "precision": args.precision,
+            "points_per_pass": args.max_points, "parallelism": "single GPU",
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "k_locate_mfma (trust-region Newton on FP64 matrix cores)",
-            "achieved": achieved,
+            "kernel": ("k_locate_mfma<8> (trust-region Newton, FP64 matrix cores), first pass"
+                       if head == fp.FP_PREC_FP64 else
+                       "k_locate_mixed<8> (FP32 Newton + FP64 end game), first pass"),
+            "achieved": sh["locate_tflops"],
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_TFLOPS,
+            "frac": sh["locate_tflops"] / PEAK_FP64_TFLOPS,
             "traffic": traffic,
-            "alg_flops_per_launch": alg_flops,
-            "launch_ms": loc_ms,
-            "candidates_per_point": c_alg,
-            "newton_iters_per_candidate": K_alg,
+            "alg_flops_per_launch": sh["locate_alg_flops_per_launch"],
+            "launch_ms": sh["breakdown_ms"]["locate_kernel"],
+            "candidates_per_point": sh["first_pass_pairs_per_point"],
+            "newton_iters_per_candidate": sh["first_pass_newton_iters_per_pair"],
         },
-        "breakdown_ms": {
-            "locate_kernel": loc_ms,
-            "eval_kernel": ev_ms,
-            "findpts": tim["findpts"][0] / max(tim["findpts"][1], 1),
-            "findpts_eval": tim["findpts_eval"][0] / max(tim["findpts_eval"][1], 1),
-            "setup_s": setup_s,
-        },
-        "gpu_counts": {"pairs_per_point": c_gpu, "newton_iters_per_pair": K_gpu,
-                       "method_candidates_per_point": cands / max(located, 1),
-                       "codes": codes.tolist()},
+        "breakdown_ms": dict(sh["breakdown_ms"], setup_s=setup_s),
+        "gpu_counts": {k: sh[k] for k in ("pairs_per_point", "newton_iters_per_pair",
+                                          "method_candidates_per_point", "codes")},
+        pname[other]: so,
+        "fp64_vs_mixed": agreement(res[fp.FP_PREC_FP64], res[fp.FP_PREC_MIXED], nf),
     }
-    # moving mesh: re-setup on the device after each rigid rotation (0.01 rad)
-    # of the annulus, then findpts + findpts_eval on the moved mesh
-    import math
-    upd = []
-    for k in range(1, 1 if args.headline_only else 6):
-        c, sn = math.cos(0.01 * k), math.sin(0.01 * k)
-        xk = (c * mesh.x - sn * mesh.y).contiguous()
-        yk = (sn * mesh.x + c * mesh.y).contiguous()
+    del res
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline(w.Mesh(mesh.name, N, mesh.x, mesh.y, mesh.z), pts,
+                                           fields, "the large-box workload", args.cpu_seconds)
+    del mesh, pts, fields
+    torch.cuda.empty_cache()
+
+    legs = {}
+    if not args.headline_only:
+        # ---- the annulus, both precisions, then a moving-mesh re-setup -------
+        m2 = w.annulus_c2(device=dev)
+        p2 = w.queries_c2(device=dev)
+        f2, _ = w.poly_fields(m2, 4, degree=7, seed=2)
+        h2, s2, r2, step2 = run_workload(fp, dev, m2, p2, f2, args.steps, args.warmup, 1 << 20,
+                                         (fp.FP_PREC_FP64, fp.FP_PREC_MIXED))
+        legs["annulus_c2"] = {
+            "workload": "16,384 curved hexes N=7 (64x16x16, exact arcs), 1,010,000 points "
+                        "(1% outside), 4 f64 fields",
+            "fp64": summarize(7, p2.shape[0], 4, r2[fp.FP_PREC_FP64]),
+            "mixed": summarize(7, p2.shape[0], 4, r2[fp.FP_PREC_MIXED]),
+            "fp64_vs_mixed": agreement(r2[fp.FP_PREC_FP64], r2[fp.FP_PREC_MIXED], 4),
+            "setup_s": s2,
+        }
+        del r2
+        fp.findpts_set_precision(h2, fp.FP_PREC_FP64)
+        upd = []
+        for k in range(1, 6):
+            c, sn = math.cos(0.01 * k), math.sin(0.01 * k)
+            xk = (c * m2.x - sn * m2.y).contiguous()
+            yk = (sn * m2.x + c * m2.y).contiguous()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fp.findpts_update(h2, xk, yk, m2.z)
+            torch.cuda.synchronize()
+            upd.append(time.perf_counter() - t0)
+        ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ea.record(stream)
+        step2()
+        eb.record(stream)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        fp.findpts_update(h, xk, yk, mesh.z)
-        torch.cuda.synchronize()
-        upd.append(time.perf_counter() - t0)
-    fp.findpts_set_precision(h, head)
-    if upd:
-        ev2a, ev2b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev2a.record(stream)
-        step()
-        ev2b.record(stream)
-        torch.cuda.synchronize()
-        moved_codes = np.bincount(code.cpu().numpy(), minlength=3).tolist()
-        rec["moving_mesh"] = {
+        legs["annulus_c2"]["moving_mesh"] = {
             "update_ms": 1e3 * float(np.median(upd)), "updates": len(upd),
-            "setup_ms": 1e3 * setup_s, "step_ms_after_update": ev2a.elapsed_time(ev2b),
-            "codes_after_update": moved_codes,
+            "step_ms_after_update": ea.elapsed_time(eb)}
+        h2.free()
+        del m2, p2, f2
+
+        # ---- the unit cube -------------------------------------------------
+        m1 = w.cube_c1(device=dev)
+        p1 = w.queries_c1(device=dev)
+        f1 = [(m1.x ** 2 + m1.y * m1.z + m1.z ** 3).contiguous()]
+        h1, s1, r1, _ = run_workload(fp, dev, m1, p1, f1, args.steps, args.warmup, 1 << 14,
+                                     (fp.FP_PREC_FP64,))
+        legs["unit_cube_c1"] = {"workload": "64 perturbed hexes N=5, 10,000 points, 1 field",
+                                "fp64": summarize(5, p1.shape[0], 1, r1[fp.FP_PREC_FP64])}
+        h1.free()
+
+        # ---- two sessions, 1.2e6 interface-face points ----------------------
+        m3 = w.overlap_c3(device=dev)
+        p3, t3 = w.queries_c3(n=1_200_000, device=dev)
+        f3, _ = w.poly_fields(m3, 4, degree=7, seed=3)
+        h3, s3, r3, _ = run_workload(fp, dev, m3, p3, f3, args.steps, args.warmup, 1 << 21,
+                                     (fp.FP_PREC_FP64, fp.FP_PREC_MIXED), psess=t3)
+        legs["two_sessions_c3"] = {
+            "workload": "box with a hole (19,360 hexes) + annulus (8,000), N=7, 1,200,000 "
+                        "interface-face points tagged by session, distance discriminator, "
+                        "4 f64 fields",
+            "fp64": summarize(7, p3.shape[0], 4, r3[fp.FP_PREC_FP64]),
+            "mixed": summarize(7, p3.shape[0], 4, r3[fp.FP_PREC_MIXED]),
+            "fp64_vs_mixed": agreement(r3[fp.FP_PREC_FP64], r3[fp.FP_PREC_MIXED], 4),
         }
-    oname = "mixed" if other == fp.FP_PREC_MIXED else "fp64"
-    rec[oname] = {
-        "value": P / (ms_o / 1e3), "ms_per_step": ms_o,
-        "locate_kernel_ms": tim_o["locate_kernel"][0] / max(tim_o["locate_kernel"][1], 1),
-        "newton_iters_per_pair": counts_o[1] / max(counts_o[0], 1),
-    }
-    rec["fp64_vs_mixed"] = agree
-    if cb:
-        rec["cpu_baseline"] = {
-            "value": cb["n"] / cb["seconds"],
-            "unit": "points/s",
-            "cores": cb["cores"],
-            "kind": "oracle",
-            "sample": f"first {cb['n']} of the same {P} query points, findpts + "
-                      f"findpts_eval of the 4 fields (plain C double, OpenMP), "
-                      f"{cb['seconds']:.1f} s",
-            "method_candidates_per_point": cb["c"],
-            "method_newton_iters_per_candidate": cb["K"],
-            "one_core_points_per_s": cb["one_core"],
-        }
-    h.free()
+        h3.free()
+        del r3, m3, p3, t3, f3
+        torch.cuda.empty_cache()
+
     # the library's plain copy kernel over 1 GiB: the achievable HBM stream rate
     # beside the 8 TB/s datasheet figure (not in counter runs, whose only copy
     # launches are the --copy-mib reference)
@@ -598,17 +681,18 @@ def main():
         rec["copy_GBps"] = 2 * nb * 5 / (ca.elapsed_time(cb_) / 1e3) / 1e9
         del src, dst
     if not args.headline_only:
-        rec["spiral"] = spiral_bench(fp, w, dev)
-        print(f"# spiral: {rec['spiral']}", file=sys.stderr, flush=True)
-        rec["schwarz_exchange"] = schwarz_bench(fp, w, dev, head)
-        print(f"# schwarz exchange: {rec['schwarz_exchange']}", file=sys.stderr, flush=True)
-        rec["twod"] = twod_bench(fp, w, dev)
-        print(f"# 2D: {rec['twod']}", file=sys.stderr, flush=True)
-    if args.serving_requests > 0:
-        sv = serving_bench(fp, w, dev, head, args.serving_requests, args.serving_warmup)
-        rec["serving"] = sv
-        mid = sv["poisson"][1]
-        rec["p50_ms"], rec["p99_ms"] = mid["p50_ms"], mid["p99_ms"]
+        legs["spiral"] = spiral_bench(fp, w, dev)
+        print(f"# spiral: {legs['spiral']}", file=sys.stderr, flush=True)
+        legs["schwarz_exchange"] = schwarz_bench(fp, w, dev, head)
+        print(f"# schwarz exchange: {legs['schwarz_exchange']}", file=sys.stderr, flush=True)
+        legs["twod"] = twod_bench(fp, w, dev)
+        print(f"# 2D: {legs['twod']}", file=sys.stderr, flush=True)
+        if args.serving_requests > 0:
+            sv = serving_bench(fp, w, dev, head, args.serving_requests, args.serving_warmup)
+            legs["serving"] = sv
+            mid = sv["poisson"][1]
+            rec["p50_ms"], rec["p99_ms"] = mid["p50_ms"], mid["p99_ms"]
+        rec["legs"] = legs
     print(json.dumps(rec), flush=True)
     if args.copy_mib > 0:
         n = args.copy_mib << 20

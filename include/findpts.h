@@ -175,22 +175,25 @@ FP_API int findpts_set_precision(fp_handle *h, int precision);
 
 /*
  * findpts_stats -- cumulative counters since setup (or the last reset),
- * written to host memory (4 values): h_counts[0] = (point, element) pairs
+ * written to host memory (6 values): h_counts[0] = (point, element) pairs
  * solved by Newton, h_counts[1] = Newton iterations, h_counts[2] = points
  * located, h_counts[3] = candidates of the method (hash cell + axis-aligned
  * element box + session test; the library solves only those whose oriented
  * box also holds the point, then redoes points left without an inside
- * element with all of them).  Synchronises the device.  reset != 0 zeroes
- * them afterwards.
+ * element with all of them), h_counts[4] and h_counts[5] = the pairs and
+ * iterations of [0] and [1] that the first-pass Newton launches solved (the
+ * rest belong to the second passes).  Synchronises the device.  reset != 0
+ * zeroes them afterwards.
  */
 FP_API int findpts_stats(fp_handle *h, long long *h_counts, int reset);
 
 /*
  * Per-kernel timing with HIP events recorded on the call's stream.
  * findpts_timing(h, 1) turns recording on; findpts_timing_read fills
- * h_ms[4] with the summed milliseconds and h_n[4] with the launch counts of
- * [0] the Newton (locate) kernel, [1] the interpolation kernel,
- * [2] whole findpts calls, [3] whole findpts_eval calls, then clears them.
+ * h_ms[5] with the summed milliseconds and h_n[5] with the launch counts of
+ * [0] the first-pass Newton (locate) kernel, [1] the interpolation kernel,
+ * [2] whole findpts calls, [3] whole findpts_eval calls, [4] the
+ * second-pass Newton kernel, then clears them.
  * findpts_timing_read synchronises the recorded events.
  */
 FP_API int findpts_timing(fp_handle *h, int enable);

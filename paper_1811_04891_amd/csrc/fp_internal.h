@@ -14,6 +14,8 @@ namespace fp {
 
 constexpr int kMaxN1 = 16;       // N <= 15
 constexpr int kMaxEvalFields = 8; // fields per interpolation launch
+constexpr int kStats = 6;          // device counters of a handle (findpts_stats)
+constexpr int kTimedPhases = 5;    // timed phases (findpts_timing_read)
 constexpr int kWave = 64;
 
 // GLL nodes z_i and barycentric weights wb_i = 1 / prod_{m != i} (z_i - z_m),
@@ -117,7 +119,8 @@ struct fp_handle {
     int scan_tmp_n = 0;
 
     // [pairs solved, Newton iterations, points located, axis-aligned box
-    //  candidates (the hash + box candidate count of the method)]
+    //  candidates (the hash + box candidate count of the method), pairs
+    //  solved by first passes, their Newton iterations]
     unsigned long long *stats = nullptr;
 
     fp::Basis basis{};

@@ -526,7 +526,7 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
 __global__ __launch_bounds__(1024) void k_stats(const unsigned *cand_part, int nb,
                                                 const unsigned *iter_part, int ni, int E,
                                                 const int *elem_off, long long located,
-                                                unsigned long long *stats)
+                                                int first, unsigned long long *stats)
 {
     __shared__ unsigned long long sc[1024 / kWave], si[1024 / kWave];
     unsigned long long c = 0, it = 0;
@@ -550,6 +550,10 @@ __global__ __launch_bounds__(1024) void k_stats(const unsigned *cand_part, int n
         }
         atomicAdd(&stats[0], (unsigned long long)elem_off[E]);
         atomicAdd(&stats[1], I);
+        if (first) {
+            atomicAdd(&stats[4], (unsigned long long)elem_off[E]);
+            atomicAdd(&stats[5], I);
+        }
         if (located) atomicAdd(&stats[2], (unsigned long long)located);
         if (C) atomicAdd(&stats[3], C);
     }
@@ -785,7 +789,7 @@ int run_findpts(fp_handle *h, const Work &w, int npts, const double *pts, const 
         if (timed) FP_HIP(hipEventRecord(l1, s));
         k_select<<<pb, 256, 0, s>>>(a, co, eo, ro, dO);
         FP_HIP(hipGetLastError());
-        k_stats<<<1, 1024, 0, s>>>(w.cand_part, pb, w.iter_part, nblk, h->E, w.elem_off, n,
+        k_stats<<<1, 1024, 0, s>>>(w.cand_part, pb, w.iter_part, nblk, h->E, w.elem_off, n, 1,
                                    h->stats);
         FP_HIP(hipGetLastError());
         // second pass over the flagged tasks with the axis-aligned candidates
@@ -799,10 +803,20 @@ int run_findpts(fp_handle *h, const Work &w, int npts, const double *pts, const 
         FP_HIP(scan_exclusive(w.elem_cnt, w.elem_off, h->E, w.scan_tmp, s));
         k_scatter<<<pb, 256, 0, s>>>(a);
         FP_HIP(hipGetLastError());
+        hipEvent_t m0 = nullptr, m1 = nullptr;
+        if (timed) {
+            m0 = pool_event(h);
+            m1 = pool_event(h);
+            FP_HIP(hipEventRecord(m0, s));
+        }
         FP_HIP(launch_locate_kernel(h, a, n, s, &nblk));
+        if (timed) {
+            FP_HIP(hipEventRecord(m1, s));
+            record(h, 4, m0, m1);
+        }
         k_select<<<pb, 256, 0, s>>>(a, co, eo, ro, dO);
         FP_HIP(hipGetLastError());
-        k_stats<<<1, 1024, 0, s>>>(w.cand_part, 0, w.iter_part, nblk, h->E, w.elem_off, 0,
+        k_stats<<<1, 1024, 0, s>>>(w.cand_part, 0, w.iter_part, nblk, h->E, w.elem_off, 0, 0,
                                    h->stats);
         FP_HIP(hipGetLastError());
         if (timed) {

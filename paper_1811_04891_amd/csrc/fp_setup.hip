@@ -785,7 +785,7 @@ extern "C" int findpts_setup(fp_handle **out, const double *x, const double *y,
     FP_HIP_H(dalloc(h, &h->bbox, 6 * (size_t)E));
     FP_HIP_H(dalloc(h, &h->obb, 18 * (size_t)E));
     FP_HIP_H(dalloc(h, &h->erec, 16 * (size_t)E));
-    FP_HIP_H(dalloc(h, &h->stats, 4));
+    FP_HIP_H(dalloc(h, &h->stats, kStats));
     FP_HIP_H(dalloc(h, &h->d_basis, 2 * kMaxN1));
     FP_HIP_H(dalloc(h, &h->d_basis32, 2 * kMaxN1));
     FP_HIP_H(dalloc(h, &h->d_flag, 1));
@@ -794,7 +794,7 @@ extern "C" int findpts_setup(fp_handle **out, const double *x, const double *y,
     FP_HIP_H(dalloc(h, &h->d_dnode, (size_t)(n1 * n1)));
     FP_HIP_H(hipMemcpyAsync(h->d_basis, &h->basis, sizeof(Basis), hipMemcpyHostToDevice, s));
     FP_HIP_H(hipMemcpyAsync(h->d_basis32, &h->basis32, sizeof(Basis32), hipMemcpyHostToDevice, s));
-    FP_HIP_H(hipMemsetAsync(h->stats, 0, 4 * sizeof(unsigned long long), s));
+    FP_HIP_H(hipMemsetAsync(h->stats, 0, kStats * sizeof(unsigned long long), s));
     {
         const std::vector<double> binv = bernstein_to_nodal_inverse(N, h->basis.z);
         const std::vector<double> dnode = node_derivatives(h->basis, N);
@@ -872,10 +872,10 @@ extern "C" int findpts_stats(fp_handle *h, long long *h_counts, int reset)
         set_error("findpts_stats: NULL argument");
         return FP_EINVAL;
     }
-    unsigned long long v[4];
+    unsigned long long v[kStats];
     FP_HIP(hipDeviceSynchronize());
     FP_HIP(hipMemcpy(v, h->stats, sizeof v, hipMemcpyDeviceToHost));
-    for (int i = 0; i < 4; ++i) h_counts[i] = (long long)v[i];
+    for (int i = 0; i < kStats; ++i) h_counts[i] = (long long)v[i];
     if (reset) FP_HIP(hipMemset(h->stats, 0, sizeof v));
     return FP_OK;
 }
@@ -967,7 +967,7 @@ extern "C" int findpts_timing_read(fp_handle *h, double *h_ms, long long *h_n)
         set_error("findpts_timing_read: NULL argument");
         return FP_EINVAL;
     }
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < kTimedPhases; ++i) {
         h_ms[i] = 0.0;
         h_n[i] = 0;
     }
@@ -975,7 +975,7 @@ extern "C" int findpts_timing_read(fp_handle *h, double *h_ms, long long *h_n)
         FP_HIP(hipEventSynchronize(t.b));
         float ms = 0.0f;
         FP_HIP(hipEventElapsedTime(&ms, t.a, t.b));
-        if (t.phase >= 0 && t.phase < 4) {
+        if (t.phase >= 0 && t.phase < kTimedPhases) {
             h_ms[t.phase] += ms;
             h_n[t.phase] += 1;
         }

@@ -232,12 +232,13 @@ def findpts_set_precision(h: Handle, precision: int):
     _check(lib().findpts_set_precision(h.ptr, int(precision)), "findpts_set_precision")
 
 
-def findpts_stats(h: Handle, reset: bool = False):
+def findpts_stats(h: Handle, reset: bool = False, first_pass: bool = False):
     """(pairs solved, Newton iterations, points located, method candidates)
-    since setup/reset."""
-    v = (C.c_longlong * 4)()
+    since setup/reset; with first_pass, also (pairs, iterations) of the
+    first-pass Newton launches."""
+    v = (C.c_longlong * 6)()
     _check(lib().findpts_stats(h.ptr, v, int(bool(reset))), "findpts_stats")
-    return tuple(v)
+    return tuple(v) if first_pass else tuple(v)[:4]
 
 
 def findpts_timing(h: Handle, enable: bool = True):
@@ -245,11 +246,12 @@ def findpts_timing(h: Handle, enable: bool = True):
 
 
 def findpts_timing_read(h: Handle):
-    """{phase: (total ms, launches)} for locate kernel, eval kernel, findpts, findpts_eval."""
-    ms, n = (C.c_double * 4)(), (C.c_longlong * 4)()
+    """{phase: (total ms, launches)} for the first-pass locate kernel, eval
+    kernel, findpts, findpts_eval and the second-pass locate kernel."""
+    ms, n = (C.c_double * 5)(), (C.c_longlong * 5)()
     _check(lib().findpts_timing_read(h.ptr, ms, n), "findpts_timing_read")
-    names = ("locate_kernel", "eval_kernel", "findpts", "findpts_eval")
-    return {names[i]: (ms[i], n[i]) for i in range(4)}
+    names = ("locate_kernel", "eval_kernel", "findpts", "findpts_eval", "locate_kernel_2")
+    return {names[i]: (ms[i], n[i]) for i in range(5)}
 
 
 def findpts_get_bbox(h: Handle):
