@@ -5,7 +5,7 @@ the large box, 200,000 sine-perturbed hexahedra of order 7 (100 x 50 x 40
 on [0,2] x [0,1] x [0,0.8], 68.6 M unique GLL points), 2e7 query points
 clustered near 8 random interior spheres (normal offsets N(0, 0.01^2), in
 random order; points outside the domain kept), 5 float64 fields given as
-random polynomials of total degree 7, in passes of 5e6 points.  All inputs
+random polynomials of total degree 7, in one pass of 2e7 points.  All inputs
 are synthetic, seeded, built on the device and resident in HBM before timing
 starts.  Both precisions are timed; --precision picks the headline one.
 
@@ -501,7 +501,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--points", type=int, default=20_000_000,
                     help="query points of the headline workload")
-    ap.add_argument("--max-points", type=int, default=5_000_000,
+    ap.add_argument("--max-points", type=int, default=20_000_000,
                     help="points per findpts pass (the handle's workspace)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)

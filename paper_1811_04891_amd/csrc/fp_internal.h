@@ -60,6 +60,7 @@ struct Work {
     double *res_dl = nullptr; // M x MC: delta at the candidate (if delta)
     int *res_in = nullptr;    // M x MC: inside flag
     int *redo = nullptr;      // M: second-pass flag per point
+    int *gate = nullptr;      // 1: nonzero when the first pass flagged any point
     int *scan_tmp = nullptr;  // block sums of the device scans
     unsigned *cand_part = nullptr;  // ceil(M / 256): per-block candidate counts
     unsigned *iter_part = nullptr;  // unit_grid(E, M, kUnitMin): Newton iterations per block
@@ -215,6 +216,10 @@ inline int unit_grid(int ns, long long n, int K)
     return (int)(g < 1 ? 1 : (g > 0x7fffffffLL ? 0x7fffffffLL : g));
 }
 
+// Grid of a second-pass launch: usually nearly empty, so a bounded grid walks
+// the units with its grid-stride loop instead of one block per element.
+constexpr int kSecondPassGrid = 8192;
+
 // Rank of each active lane's entry in its group's counter, cnt[e] += 1 per
 // entry.  Lanes of a wavefront that share the group of the first pending
 // lane take their ranks from one atomic add (up to four such groups); any
@@ -245,10 +250,12 @@ __device__ __forceinline__ int wave_rank(int *cnt, int e, bool act)
 constexpr int kUnitMin = 64;  // smallest K of the locate kernels
 
 // Exclusive scan of n ints: out[0..n], out[n] = total.  tmp needs
-// scan_tmp_size(n) ints.
+// scan_tmp_size(n) ints.  With gate non-null the kernels do nothing while
+// *gate is zero (a pass with no work), as does the gated fill.
 int scan_tmp_size(long long n);
 hipError_t scan_exclusive(const int *in, int *out, int n, int *tmp,
-                          hipStream_t s);
+                          hipStream_t s, const int *gate = nullptr);
+hipError_t fill_int_gated(int *p, int value, long long n, const int *gate, hipStream_t s);
 
 // GLL nodes and barycentric weights of order N; the inverse of the
 // Bernstein-to-nodal matrix (n1 x n1, row-major), both computed on the host.

@@ -17,6 +17,7 @@
 //   k_locate   (orders 8..15) one wavefront per work unit of 64 pairs,
 //              lanes = pairs, node rows through scalar loads
 //   k_select   per point: classification and owner rule, caller's order
+#include <algorithm>
 #include <cmath>
 
 #include "fp_basis.h"
@@ -33,6 +34,9 @@ struct LocArgs {
     int *redo;           // first pass writes 1 for tasks left without an inside
                          // candidate and with a partial candidate set, else 0
     const int *only;     // non-null (second pass): tasks with only[t] != 0
+    int *gate;           // first pass: cleared by k_cand, set by k_select when any
+                         // task is flagged; second pass: every kernel returns at
+                         // once while it is zero
     const double *delta;
     const int *esess;
     const int *cell_off;
@@ -88,6 +92,8 @@ constexpr int kCountMask = (1 << kFullBit) - 1;
 // slot that keeps its first-pass result.
 __global__ __launch_bounds__(256) void k_cand(LocArgs a)
 {
+    if (a.only && !*a.gate) return;  // second pass with nothing flagged
+    if (a.obb && blockIdx.x == 0 && threadIdx.x == 0) *a.gate = 0;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     int naabb = 0, n = 0, n1st = 0;
     if (t < a.npts && a.only && !a.only[t]) {
@@ -191,6 +197,7 @@ __global__ __launch_bounds__(256) void k_cand(LocArgs a)
 
 __global__ __launch_bounds__(256) void k_scatter(LocArgs a)
 {
+    if (a.only && !*a.gate) return;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.npts) return;
     const int n = a.ncand[p] & kCountMask;  // 0 for tasks the pass skips
@@ -460,6 +467,7 @@ template <int N1>
 __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__restrict__ basis,
                                                   const double *__restrict__ dnode)
 {
+    if (a.only && !*a.gate) return;
     constexpr int V = N1 * N1 * N1;
     const BasisPtr<double> B{as_const(basis)};
     unsigned long long my_iters = 0;
@@ -521,17 +529,22 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
 
 #include "fp_mfma.inc"
 
-// Fold one pass's partial counts into the handle's counters: one block, so
-// the counters see a handful of atomics per pass.
+constexpr int kStatsBlocks = 32;
+
+// Fold one pass's partial counts into the handle's counters: a few blocks,
+// each adding its share with one atomic per counter.
 __global__ __launch_bounds__(1024) void k_stats(const unsigned *cand_part, int nb,
                                                 const unsigned *iter_part, int ni, int E,
                                                 const int *elem_off, long long located,
-                                                int first, unsigned long long *stats)
+                                                int first, const int *gate,
+                                                unsigned long long *stats)
 {
+    if (gate && !*gate) return;
     __shared__ unsigned long long sc[1024 / kWave], si[1024 / kWave];
     unsigned long long c = 0, it = 0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) c += cand_part[i];
-    for (int i = threadIdx.x; i < ni; i += blockDim.x) it += iter_part[i];
+    const int stride = blockDim.x * gridDim.x;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += stride) c += cand_part[i];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ni; i += stride) it += iter_part[i];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         c += __shfl_xor(c, o, kWave);
@@ -548,13 +561,14 @@ __global__ __launch_bounds__(1024) void k_stats(const unsigned *cand_part, int n
             C += sc[w];
             I += si[w];
         }
-        atomicAdd(&stats[0], (unsigned long long)elem_off[E]);
-        atomicAdd(&stats[1], I);
+        const unsigned long long pairs = blockIdx.x == 0 ? (unsigned long long)elem_off[E] : 0ull;
+        if (pairs) atomicAdd(&stats[0], pairs);
+        if (I) atomicAdd(&stats[1], I);
         if (first) {
-            atomicAdd(&stats[4], (unsigned long long)elem_off[E]);
-            atomicAdd(&stats[5], I);
+            if (pairs) atomicAdd(&stats[4], pairs);
+            if (I) atomicAdd(&stats[5], I);
         }
-        if (located) atomicAdd(&stats[2], (unsigned long long)located);
+        if (located && blockIdx.x == 0) atomicAdd(&stats[2], (unsigned long long)located);
         if (C) atomicAdd(&stats[3], C);
     }
 }
@@ -565,6 +579,7 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
                                                 int *__restrict__ el, double *__restrict__ rst,
                                                 double *__restrict__ dist2)
 {
+    if (a.only && !*a.gate) return;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (!task_on(a, t)) return;
     const int p = t;
@@ -650,6 +665,9 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
                     redo = true;
         }
         a.redo[t] = redo ? 1 : 0;
+        // open the second pass (one store per wavefront with a flagged task)
+        const unsigned long long b = __ballot(redo);
+        if (b != 0ull && (int)(threadIdx.x & (kWave - 1)) == __ffsll((long long)b) - 1) *a.gate = 1;
     }
 }
 
@@ -678,20 +696,22 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
 static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, int n,
                                        hipStream_t s, int *nblk)
 {
+#define FP_GRID(K) (a.only ? std::min(unit_grid(h->E, n, (K)), kSecondPassGrid) \
+                           : unit_grid(h->E, n, (K)))
 #define FP_LAUNCH_LOCATE(N1)                                      \
     do {                                                          \
-        *nblk = unit_grid(h->E, n, kUnitScalar);                  \
+        *nblk = FP_GRID(kUnitScalar);                             \
         k_locate<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_dnode); \
     } while (0)
 // mixed precision: first pass only (the second pass is binary64)
 #define FP_LAUNCH_MFMA(N1)                                                           \
     do {                                                                             \
         if (h->precision == FP_PREC_MIXED && a.obb) {                                \
-            *nblk = unit_grid(h->E, n, kUnitMixed);                                  \
+            *nblk = FP_GRID(kUnitMixed);                                             \
             k_locate_mixed<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_basis32,  \
                                                         h->d_dnode);                 \
         } else {                                                                     \
-            *nblk = unit_grid(h->E, n, kUnitMfma);                                   \
+            *nblk = FP_GRID(kUnitMfma);                                              \
             k_locate_mfma<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_dnode);     \
         }                                                                            \
     } while (0)
@@ -715,6 +735,7 @@ static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, int
     }
 #undef FP_LAUNCH_LOCATE
 #undef FP_LAUNCH_MFMA
+#undef FP_GRID
     return hipGetLastError();
 }
 
@@ -760,6 +781,7 @@ int run_findpts(fp_handle *h, const Work &w, int npts, const double *pts, const 
         a.res_in = w.res_in;
         a.cand_part = w.cand_part;
         a.iter_part = w.iter_part;
+        a.gate = w.gate;
 
         hipEvent_t t0 = nullptr, t1 = nullptr, l0 = nullptr, l1 = nullptr;
         if (timed) {
@@ -789,18 +811,18 @@ int run_findpts(fp_handle *h, const Work &w, int npts, const double *pts, const 
         if (timed) FP_HIP(hipEventRecord(l1, s));
         k_select<<<pb, 256, 0, s>>>(a, co, eo, ro, dO);
         FP_HIP(hipGetLastError());
-        k_stats<<<1, 1024, 0, s>>>(w.cand_part, pb, w.iter_part, nblk, h->E, w.elem_off, n, 1,
-                                   h->stats);
+        k_stats<<<kStatsBlocks, 1024, 0, s>>>(w.cand_part, pb, w.iter_part, nblk, h->E,
+                                              w.elem_off, n, 1, nullptr, h->stats);
         FP_HIP(hipGetLastError());
         // second pass over the flagged tasks with the axis-aligned candidates
         // only (other tasks get no candidates and keep their result)
         a.obb = nullptr;
         a.redo = nullptr;
         a.only = w.redo;
-        FP_HIP(fill_int(w.elem_cnt, 0, (long long)h->E + 1, s));
+        FP_HIP(fill_int_gated(w.elem_cnt, 0, (long long)h->E + 1, w.gate, s));
         k_cand<<<pb, 256, 0, s>>>(a);
         FP_HIP(hipGetLastError());
-        FP_HIP(scan_exclusive(w.elem_cnt, w.elem_off, h->E, w.scan_tmp, s));
+        FP_HIP(scan_exclusive(w.elem_cnt, w.elem_off, h->E, w.scan_tmp, s, w.gate));
         k_scatter<<<pb, 256, 0, s>>>(a);
         FP_HIP(hipGetLastError());
         hipEvent_t m0 = nullptr, m1 = nullptr;
@@ -816,8 +838,8 @@ int run_findpts(fp_handle *h, const Work &w, int npts, const double *pts, const 
         }
         k_select<<<pb, 256, 0, s>>>(a, co, eo, ro, dO);
         FP_HIP(hipGetLastError());
-        k_stats<<<1, 1024, 0, s>>>(w.cand_part, 0, w.iter_part, nblk, h->E, w.elem_off, 0, 0,
-                                   h->stats);
+        k_stats<<<kStatsBlocks, 1024, 0, s>>>(w.cand_part, 0, w.iter_part, nblk, h->E,
+                                              w.elem_off, 0, 0, w.gate, h->stats);
         FP_HIP(hipGetLastError());
         if (timed) {
             FP_HIP(hipEventRecord(t1, s));

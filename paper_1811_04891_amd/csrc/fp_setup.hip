@@ -520,6 +520,7 @@ void lay_out(Layout &L, Work &w, int E, int MC, int M, bool delta)
     w.res_dl = delta ? L.take<double>(m * mc) : nullptr;
     w.res_in = L.take<int>(m * mc);
     w.redo = L.take<int>(m);
+    w.gate = L.take<int>(1);
     w.scan_tmp = L.take<int>((size_t)scan_tmp_size((long long)E + 1));
     w.cand_part = L.take<unsigned>((m + 255) / 256);
     w.iter_part = L.take<unsigned>((size_t)unit_grid(E, M, kUnitMin));

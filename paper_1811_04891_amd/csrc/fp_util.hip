@@ -58,8 +58,9 @@ __device__ __forceinline__ int block_excl_scan(int v, int *total)
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(
-    const int *__restrict__ in, int n, int *__restrict__ tsum)
+    const int *__restrict__ in, int n, int *__restrict__ tsum, const int *__restrict__ gate)
 {
+    if (gate && !*gate) return;
     const long long base = (long long)blockIdx.x * kScanTile;
     int s = 0;
 #pragma unroll
@@ -73,8 +74,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_top(int *__restrict__ tsum,
-                                                           int nt)
+                                                           int nt, const int *__restrict__ gate)
 {
+    if (gate && !*gate) return;
     // each thread scans a contiguous run of tile sums
     const int per = (nt + kScanThreads - 1) / kScanThreads;
     const int b = threadIdx.x * per;
@@ -93,8 +95,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_top(int *__restrict__ tsu
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(
     const int *__restrict__ in, int n, const int *__restrict__ toff,
-    int *__restrict__ out, int nt)
+    int *__restrict__ out, int nt, const int *__restrict__ gate)
 {
+    if (gate && !*gate) return;
     const long long base = (long long)blockIdx.x * kScanTile;
     // each thread owns kScanItems consecutive items
     const long long my = base + (long long)threadIdx.x * kScanItems;
@@ -121,21 +124,23 @@ __global__ void k_zero_total(int *out, int n) { out[n] = 0; }
 
 int scan_tmp_size(long long n) { return (int)((n + kScanTile - 1) / kScanTile) + 1; }
 
-hipError_t scan_exclusive(const int *in, int *out, int n, int *tmp, hipStream_t s)
+hipError_t scan_exclusive(const int *in, int *out, int n, int *tmp, hipStream_t s,
+                          const int *gate)
 {
     if (n <= 0) {
         k_zero_total<<<1, 1, 0, s>>>(out, 0);
         return hipGetLastError();
     }
     const int nt = (n + kScanTile - 1) / kScanTile;
-    k_scan_tiles<<<nt, kScanThreads, 0, s>>>(in, n, tmp);
-    k_scan_top<<<1, kScanThreads, 0, s>>>(tmp, nt);
-    k_scan_down<<<nt, kScanThreads, 0, s>>>(in, n, tmp, out, nt);
+    k_scan_tiles<<<nt, kScanThreads, 0, s>>>(in, n, tmp, gate);
+    k_scan_top<<<1, kScanThreads, 0, s>>>(tmp, nt, gate);
+    k_scan_down<<<nt, kScanThreads, 0, s>>>(in, n, tmp, out, nt, gate);
     return hipGetLastError();
 }
 
-__global__ void k_fill_int(int *__restrict__ p, int v, long long n)
+__global__ void k_fill_int(int *__restrict__ p, int v, long long n, const int *__restrict__ gate)
 {
+    if (gate && !*gate) return;
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     long long stride = (long long)gridDim.x * blockDim.x;
     for (; i < n; i += stride) p[i] = v;
@@ -146,7 +151,16 @@ hipError_t fill_int(int *p, int value, long long n, hipStream_t s)
     if (n <= 0) return hipSuccess;
     long long blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    k_fill_int<<<(int)blocks, 256, 0, s>>>(p, value, n);
+    k_fill_int<<<(int)blocks, 256, 0, s>>>(p, value, n, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t fill_int_gated(int *p, int value, long long n, const int *gate, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    k_fill_int<<<(int)blocks, 256, 0, s>>>(p, value, n, gate);
     return hipGetLastError();
 }
 
