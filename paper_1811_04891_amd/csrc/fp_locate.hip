@@ -208,6 +208,16 @@ __global__ __launch_bounds__(256) void k_scatter(LocArgs a)
     }
 }
 
+// 1 / x from the hardware reciprocal and two Newton-Raphson refinements
+// (within an ulp or two of the quotient, no scaling for denormals: the
+// trust-region step it scales does not need a correctly rounded quotient).
+__device__ __forceinline__ double rcp64(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(fma(-x, y, 1.0), y, y);
+    return fma(fma(-x, y, 1.0), y, y);
+}
+
 // Solve the 3x3 system A d = b by Cramer's rule; false if det is 0 or the
 // result is not finite.
 __device__ __forceinline__ bool solve3(const double (&A)[9], const double (&b)[3],
@@ -223,7 +233,7 @@ __device__ __forceinline__ bool solve3(const double (&A)[9], const double (&b)[3
     const double c20 = A[1] * A[5] - A[2] * A[4];
     const double c21 = A[2] * A[3] - A[0] * A[5];
     const double c22 = A[0] * A[4] - A[1] * A[3];
-    const double inv = 1.0 / det;
+    const double inv = rcp64(det);
     d[0] = (c00 * b[0] + c10 * b[1] + c20 * b[2]) * inv;
     d[1] = (c01 * b[0] + c11 * b[1] + c21 * b[2]) * inv;
     d[2] = (c02 * b[0] + c12 * b[1] + c22 * b[2]) * inv;
@@ -291,11 +301,13 @@ struct TRNewton {
         const double phit = fma(Ft[2], Ft[2], fma(Ft[1], Ft[1], Ft[0] * Ft[0]));
         bool acc = true, stop = false;
         if (have) {
-            const double rho = (phi - phit) / pred;
-            acc = rho >= 0.01;
-            if (rho > 0.75 && limited)
+            // rho = (phi - phit) / pred against 0.01, 0.75 and 0.25, with
+            // pred > 0 (a step is only tried when its predicted decrease is)
+            const double ared = phi - phit;
+            acc = ared >= 0.01 * pred;
+            if (ared > 0.75 * pred && limited)
                 D = fmin(2.0 * D, 2.0);
-            else if (rho < 0.25)
+            else if (ared < 0.25 * pred)
                 D = 0.25 * ns;
             if (acc && ns <= step_stop) stop = true;
         }
@@ -358,7 +370,7 @@ struct TRNewton {
         const double nd = fmax(fabs(dl[0]), fmax(fabs(dl[1]), fabs(dl[2])));
         if (!(nd > 0.0) || !isfinite(nd)) return true;
         limited = nd > D;
-        const double sc = limited ? D / nd : 1.0;
+        const double sc = limited ? D * rcp64(nd) : 1.0;
         double s[3];
         ns = 0.0;
 #pragma unroll
@@ -528,6 +540,7 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
 }
 
 #include "fp_mfma.inc"
+#include "fp_newton8.inc"
 
 constexpr int kStatsBlocks = 32;
 
@@ -710,6 +723,9 @@ static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, int
             *nblk = FP_GRID(kUnitMixed);                                             \
             k_locate_mixed<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_basis32,  \
                                                         h->d_dnode);                 \
+        } else if (N1 == kN8) {                                                      \
+            *nblk = FP_GRID(kUnitMfma);                                              \
+            k_newton8<<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_dnode);            \
         } else {                                                                     \
             *nblk = FP_GRID(kUnitMfma);                                              \
             k_locate_mfma<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_dnode);     \
