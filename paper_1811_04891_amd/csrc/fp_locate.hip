@@ -76,6 +76,11 @@ __device__ __forceinline__ bool task_on(const LocArgs &a, int t)
 // res_in of a pair: 0 = solved, not inside; 1 = inside; kUnsolved = left by the
 // mixed-precision first pass to the binary64 second pass
 constexpr int kUnsolved = 2;
+// res_in kOutside: the mixed-precision first pass found the point clearly
+// outside the element (binary32 residual far above its rounding level on a
+// face of [-1,1]^3): never inside; solved in binary64 only if the point has no
+// inside candidate (its distance is then needed)
+constexpr int kOutside = 3;
 
 // ncand[t] = candidate count | (1 << kFullBit) when the list is the method's
 // whole candidate set (no second pass needed for that point)
@@ -175,7 +180,8 @@ __global__ __launch_bounds__(256) void k_cand(LocArgs a)
     for (int k = 0; k < nmax; ++k) {
         const long long s = (long long)k * a.M + t;
         // a first-pass slot is solved again only if it was left unsolved
-        const bool act = k < n && (k >= n1st || a.res_in[s] == kUnsolved);
+        const bool act =
+            k < n && (k >= n1st || a.res_in[s] == kUnsolved || a.res_in[s] == kOutside);
         const int e = act ? a.cand_el[s] : -1;
         const int r = wave_rank(a.elem_cnt, e, act);
         if (k < n) a.cand_pos[s] = act ? r : -1;
@@ -541,6 +547,7 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
 
 #include "fp_mfma.inc"
 #include "fp_newton8.inc"
+#include "fp_mixed8.inc"
 
 constexpr int kStatsBlocks = 32;
 
@@ -601,11 +608,12 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
     const bool full = (nv >> kFullBit) != 0;
     auto S =[&](int k) { return (long long)k * a.M + t; };
     int w = -1, c = 2;
-    bool anyin = false, unsolved = false;
+    bool anyin = false, unsolved = false, outside = false;
     for (int k = 0; k < n; ++k) {
         const int in = a.res_in[S(k)];
         anyin |= in == 1;
         unsolved |= in == kUnsolved;
+        outside |= in == kOutside;
     }
     if (anyin) {
         c = 0;
@@ -639,7 +647,7 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
             for (int k = 0; k < n; ++k)
                 if (a.res_in[S(k)] == 1 && (w < 0 || a.cand_el[S(k)] < a.cand_el[S(w)])) w = k;
         }
-    } else if (unsolved) {
+    } else if (unsolved || outside) {
         c = 1;  // provisional: the second pass decides
     } else if (n > 0) {
         c = 1;
@@ -666,7 +674,7 @@ __global__ __launch_bounds__(256) void k_select(LocArgs a, int *__restrict__ cod
         dist2[p] = o[3];
     }
     if (a.obb) {
-        bool redo = c != 0 && (!full || unsolved);
+        bool redo = c != 0 && (!full || unsolved || outside);
         if (c == 0 && unsolved) {
             // a pair the binary32 phase left unsolved may be inside too: with
             // the distance field it may belong to a session with a larger
@@ -719,7 +727,10 @@ static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, int
 // mixed precision: first pass only (the second pass is binary64)
 #define FP_LAUNCH_MFMA(N1)                                                           \
     do {                                                                             \
-        if (h->precision == FP_PREC_MIXED && a.obb) {                                \
+        if (h->precision == FP_PREC_MIXED && a.obb && N1 == kN8) {                   \
+            *nblk = FP_GRID(kUnitMixed);                                             \
+            k_mixed8<<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_basis32, h->d_dnode); \
+        } else if (h->precision == FP_PREC_MIXED && a.obb) {                         \
             *nblk = FP_GRID(kUnitMixed);                                             \
             k_locate_mixed<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_basis32,  \
                                                         h->d_dnode);                 \
