@@ -515,6 +515,10 @@ def main():
     ap.add_argument("--serving-warmup", type=int, default=50)
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the headline workload (for profiler runs)")
+    ap.add_argument("--legs", default="annulus,cube,two_sessions,spiral,schwarz,twod,serving",
+                    help="comma-separated secondary legs to run")
+    ap.add_argument("--skip-headline", action="store_true",
+                    help="run only the secondary legs (no JSON headline line)")
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
                     help="precision of the headline line (the other one is timed beside it)")
     args = ap.parse_args()
@@ -536,7 +540,34 @@ def main():
     other = fp.FP_PREC_FP64 if head == fp.FP_PREC_MIXED else fp.FP_PREC_MIXED
     pname = {fp.FP_PREC_FP64: "fp64", fp.FP_PREC_MIXED: "mixed"}
 
-    # ---- headline: the large box ------------------------------------------
+    legs_on = set(args.legs.split(",")) if not args.headline_only else set()
+    rec = {}
+    if not args.skip_headline:
+        rec = headline(args, fp, w, dev, head, other, pname)
+    legs = run_legs(args, fp, w, dev, head, legs_on, stream)
+    if legs:
+        rec["legs"] = legs
+        if "serving" in legs:
+            mid = legs["serving"]["poisson"][1]
+            rec["p50_ms"], rec["p99_ms"] = mid["p50_ms"], mid["p99_ms"]
+    if "copy" in legs_on or not args.skip_headline:
+        copy_rate(args, fp, dev, stream, rec)
+    print(json.dumps(rec), flush=True)
+    if args.copy_mib > 0:
+        n = args.copy_mib << 20
+        src = torch.ones(n // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            fp.fp_copy(src, dst, stream)
+        torch.cuda.synchronize()
+        print(f"# copy kernel: {n} bytes read, {n} bytes written per launch", file=sys.stderr,
+              flush=True)
+
+
+def headline(args, fp, w, dev, head, other, pname):
+    """The large box in both precisions, its roofline and the CPU oracle."""
+    import torch
+
     mesh = w.big_box_c5(device=dev)
     pts = w.queries_c5(n=args.points, device=dev)
     fields, _ = w.poly_fields(mesh, 5, degree=7, seed=5)
@@ -597,9 +628,16 @@ def main():
                                            fields, "the large-box workload", args.cpu_seconds)
     del mesh, pts, fields
     torch.cuda.empty_cache()
+    return rec
+
+
+def run_legs(args, fp, w, dev, head, on, stream):
+    """The secondary workloads named in `on`."""
+    import numpy as np
+    import torch
 
     legs = {}
-    if not args.headline_only:
+    if "annulus" in on:
         # ---- the annulus, both precisions, then a moving-mesh re-setup -------
         m2 = w.annulus_c2(device=dev)
         p2 = w.queries_c2(device=dev)
@@ -637,6 +675,7 @@ def main():
         h2.free()
         del m2, p2, f2
 
+    if "cube" in on:
         # ---- the unit cube -------------------------------------------------
         m1 = w.cube_c1(device=dev)
         p1 = w.queries_c1(device=dev)
@@ -647,6 +686,7 @@ def main():
                                 "fp64": summarize(5, p1.shape[0], 1, r1[fp.FP_PREC_FP64])}
         h1.free()
 
+    if "two_sessions" in on:
         # ---- two sessions, 1.2e6 interface-face points ----------------------
         m3 = w.overlap_c3(device=dev)
         p3, t3 = w.queries_c3(n=1_200_000, device=dev)
@@ -665,9 +705,28 @@ def main():
         del r3, m3, p3, t3, f3
         torch.cuda.empty_cache()
 
-    # the library's plain copy kernel over 1 GiB: the achievable HBM stream rate
-    # beside the 8 TB/s datasheet figure (not in counter runs, whose only copy
-    # launches are the --copy-mib reference)
+    if "spiral" in on:
+        legs["spiral"] = spiral_bench(fp, w, dev)
+        print(f"# spiral: {legs['spiral']}", file=sys.stderr, flush=True)
+    if "schwarz" in on:
+        legs["schwarz_exchange"] = schwarz_bench(fp, w, dev, head)
+        print(f"# schwarz exchange: {legs['schwarz_exchange']}", file=sys.stderr, flush=True)
+    if "twod" in on:
+        legs["twod"] = twod_bench(fp, w, dev)
+        print(f"# 2D: {legs['twod']}", file=sys.stderr, flush=True)
+    if "serving" in on and args.serving_requests > 0:
+        # the serving stream runs in mixed precision, as its workload specifies
+        legs["serving"] = serving_bench(fp, w, dev, fp.FP_PREC_MIXED, args.serving_requests,
+                                        args.serving_warmup)
+    return legs
+
+
+def copy_rate(args, fp, dev, stream, rec):
+    """The library's plain copy kernel over 1 GiB: the achievable HBM stream
+    rate beside the 8 TB/s datasheet figure (not in counter runs, whose only
+    copy launches are the --copy-mib reference)."""
+    import torch
+
     nb = 0 if args.copy_mib > 0 else 1 << 30
     if nb:
         src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
@@ -682,30 +741,6 @@ def main():
         torch.cuda.synchronize()
         rec["copy_GBps"] = 2 * nb * 5 / (ca.elapsed_time(cb_) / 1e3) / 1e9
         del src, dst
-    if not args.headline_only:
-        legs["spiral"] = spiral_bench(fp, w, dev)
-        print(f"# spiral: {legs['spiral']}", file=sys.stderr, flush=True)
-        legs["schwarz_exchange"] = schwarz_bench(fp, w, dev, head)
-        print(f"# schwarz exchange: {legs['schwarz_exchange']}", file=sys.stderr, flush=True)
-        legs["twod"] = twod_bench(fp, w, dev)
-        print(f"# 2D: {legs['twod']}", file=sys.stderr, flush=True)
-        if args.serving_requests > 0:
-            sv = serving_bench(fp, w, dev, head, args.serving_requests, args.serving_warmup)
-            legs["serving"] = sv
-            mid = sv["poisson"][1]
-            rec["p50_ms"], rec["p99_ms"] = mid["p50_ms"], mid["p99_ms"]
-        rec["legs"] = legs
-    print(json.dumps(rec), flush=True)
-    if args.copy_mib > 0:
-        n = args.copy_mib << 20
-        src = torch.ones(n // 8, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(2):
-            fp.fp_copy(src, dst, stream)
-        torch.cuda.synchronize()
-        print(f"# copy kernel: {n} bytes read, {n} bytes written per launch", file=sys.stderr,
-              flush=True)
-
 
 if __name__ == "__main__":
     main()

@@ -166,29 +166,35 @@ __global__ __launch_bounds__(kEvThreads) void k_eval_grp(EvArgs a, FieldPtrs F,
 }
 
 // Interpolation on the matrix cores (orders 1..7): one wavefront per work
-// unit (up to kUnitEvalMfma points of one element), points in batches of 16.  For field f the first contraction
-// a_f(k, j; point) = sum_i F_f[k][j][i] h_i(r_point) is a dense product of the
-// field's rows (n1^2 x n1) with the basis values of 16 points, one
-// v_mfma_f64_16x16x4f64 per 16 rows and 4 i-values; the field's A fragments
-// stay in registers for all points of the element.  Lane n + 16 g supplies
-// h_i(r) for i = 4 kb + g of point n (evaluating only its own i and j, in its
-// rotated node order), contracts its rows j = g + 4 w with
-// h_j(s) and every plane k with h_k(t), and the 4 lanes of point n add their
-// partial sums (same order in all 4: the total is bit-identical).
+// unit (up to kUnitEvalMfma points of one element), points in batches of 16.
+// For field f the first contraction a_f(k, j; point) = sum_i F_f[k][j][i]
+// h_i(r_point) is a dense product of the field's rows (n1^2 x n1) with the
+// basis values of 16 points, one 16x16x4 matrix product per 16 rows and 4
+// i-values; the fields' A fragments stay in registers for all points of the
+// element.  Lane n + 16 g supplies h_i(r) for i = 4 kb + g of point n
+// (evaluating only its own i and j, in its rotated node order), contracts its
+// rows j = g + 4 w with h_j(s) and every plane k with h_k(t), and the 4 lanes
+// of point n add their partial sums (same order in all 4: the total is
+// bit-identical).  T is the arithmetic: binary64 (4 fields per pass), or
+// binary32 with binary32 accumulation for mixed precision (all 8 fields of a
+// launch in one pass, binary32 basis and matrix products; the nodal values
+// are rounded to binary32, the result widened to binary64).
 constexpr int kEvFieldsPerPass = 4;
 constexpr int kUnitEvalMfma = 512;  // points of one element per work unit
 
-template <int N1>
+template <int N1, class T>
 __global__ __launch_bounds__(kWave) void k_eval_mfma(EvArgs a, FieldPtrs F,
-                                                     const double *__restrict__ basis)
+                                                     const double *__restrict__ basis,
+                                                     const float *__restrict__ basis32)
 {
     using S = MShape<N1>;
     constexpr int V = N1 * N1 * N1;
     constexpr int MBF = (N1 + S::PPB - 1) / S::PPB;  // M blocks per field (planes k)
-    constexpr int NF = kEvFieldsPerPass;
+    constexpr int NF = sizeof(T) == sizeof(double) ? kEvFieldsPerPass : kMaxEvalFields;
     const BasisPtr<double> B{as_const(basis)};
-    LaneNodes<N1> Z;  // h_i(r), h_j(s) only for the lane's own i, j = g + 4 w
-    lane_nodes<N1>(B, threadIdx.x >> 4, Z);
+    const BasisPtr<float> B32{as_const(basis32)};
+    LaneNodes<N1, T> Z;  // h_i(r), h_j(s) only for the lane's own i, j = g + 4 w
+    lane_nodes<N1, T>(B, threadIdx.x >> 4, Z);
     const UnitList units(a.off, a.E, 1, a.E, kUnitEvalMfma);
     for (long long unit = blockIdx.x; unit < units.end; unit += gridDim.x) {
         Unit U;
@@ -197,10 +203,10 @@ __global__ __launch_bounds__(kWave) void k_eval_mfma(EvArgs a, FieldPtrs F,
         const int lane = threadIdx.x, n = lane & 15, g = lane >> 4;
         // A fragment coordinates of this lane: row -> plane p, row jj; column i
         const int row = lane & 15, q = lane >> 4;
-        const int gr = MF<double>::grp(row), vr = MF<double>::comp(row);
+        const int gr = MF<T>::grp(row), vr = MF<T>::comp(row);
         const int pr = vr / S::EPP, jj = gr + 4 * (vr % S::EPP);
         for (int f0 = 0; f0 < a.nf; f0 += NF) {
-            double A[NF][MBF][S::KB];
+            T A[NF][MBF][S::KB];
     #pragma unroll
             for (int f = 0; f < NF; ++f) {
                 const double *src = (f0 + f < a.nf) ? F.f[f0 + f] + (long long)e * V : nullptr;
@@ -211,7 +217,7 @@ __global__ __launch_bounds__(kWave) void k_eval_mfma(EvArgs a, FieldPtrs F,
                     for (int kb = 0; kb < S::KB; ++kb) {
                         const int i = 4 * kb + q;
                         const bool ok = src && k < N1 && jj < N1 && i < N1;
-                        A[f][mb][kb] = ok ? src[N1 * (jj + N1 * k) + i] : 0.0;
+                        A[f][mb][kb] = ok ? (T)src[N1 * (jj + N1 * k) + i] : T(0);
                     }
                 }
             }
@@ -220,25 +226,28 @@ __global__ __launch_bounds__(kWave) void k_eval_mfma(EvArgs a, FieldPtrs F,
                 const bool act = u < end;
                 const int p = a.order[act ? u : beg];
                 static_assert(S::KB == S::EPP, "r and s rows use the same lane indices");
-                double hrl[S::KB], hsl[S::EPP], ht[N1];
-                lagrange_lane<N1>(Z, a.rst[3 * (long long)p], hrl);
-                lagrange_lane<N1>(Z, a.rst[3 * (long long)p + 1], hsl);
-                lagrange<N1>(B, a.rst[3 * (long long)p + 2], ht);
+                T hrl[S::KB], hsl[S::EPP], ht[N1];
+                lagrange_lane<N1, T>(Z, (T)a.rst[3 * (long long)p], hrl);
+                lagrange_lane<N1, T>(Z, (T)a.rst[3 * (long long)p + 1], hsl);
+                if constexpr (sizeof(T) == sizeof(double))
+                    lagrange<N1>(B, a.rst[3 * (long long)p + 2], ht);
+                else
+                    lagrange<N1>(B32, (float)a.rst[3 * (long long)p + 2], ht);
     #pragma unroll
                 for (int f = 0; f < NF; ++f) {
                     if (f0 + f < a.nf) {
-                        double v = 0.0;
+                        T v = 0;
     #pragma unroll
                         for (int mb = 0; mb < MBF; ++mb) {
-                            dx4 c = {0, 0, 0, 0};
+                            typename MF<T>::acc c = {0, 0, 0, 0};
     #pragma unroll
                             for (int kb = 0; kb < S::KB; ++kb)
-                                c = MF<double>::mma(A[f][mb][kb], hrl[kb], c);
+                                c = MF<T>::mma(A[f][mb][kb], hrl[kb], c);
     #pragma unroll
                             for (int pp = 0; pp < S::PPB; ++pp) {
                                 const int k = mb * S::PPB + pp;
                                 if (k < N1) {
-                                    double sa = 0.0;
+                                    T sa = 0;
     #pragma unroll
                                     for (int w = 0; w < S::EPP; ++w)
                                         sa = fma(c[pp * S::EPP + w], hsl[w], sa);
@@ -247,7 +256,7 @@ __global__ __launch_bounds__(kWave) void k_eval_mfma(EvArgs a, FieldPtrs F,
                             }
                         }
                         v = slot_sum(v);
-                        if (act && g == 0) a.out[(f0 + f) * a.ostride + p] = v;
+                        if (act && g == 0) a.out[(f0 + f) * a.ostride + p] = (double)v;
                     }
                 }
             }
@@ -257,9 +266,17 @@ __global__ __launch_bounds__(kWave) void k_eval_mfma(EvArgs a, FieldPtrs F,
 
 // Launches the order's interpolation kernel over the work units of n points.
 static hipError_t launch_eval_kernel(int n1, int E, int n, const EvArgs &a, const FieldPtrs &F,
-                                     const double *B, hipStream_t s)
+                                     const double *B, const float *B32, bool mixed, hipStream_t s)
 {
-#define FP_LAUNCH_MFMA(N1) k_eval_mfma<N1><<<unit_grid(E, n, kUnitEvalMfma), kWave, 0, s>>>(a, F, B)
+#define FP_LAUNCH_MFMA(N1)                                                              \
+    do {                                                                                \
+        if (mixed)                                                                      \
+            k_eval_mfma<N1, float><<<unit_grid(E, n, kUnitEvalMfma), kWave, 0, s>>>(a, F, B, \
+                                                                                   B32); \
+        else                                                                            \
+            k_eval_mfma<N1, double><<<unit_grid(E, n, kUnitEvalMfma), kWave, 0, s>>>(a, F, B, \
+                                                                                    B32); \
+    } while (0)
     switch (n1) {
         case 2: FP_LAUNCH_MFMA(2); return hipGetLastError();
         case 3: FP_LAUNCH_MFMA(3); return hipGetLastError();
@@ -346,7 +363,8 @@ int run_eval(fp_handle *h, const Work &w, int npts, const int *code, const int *
                 FP_HIP(hipGetLastError());
                 if (timed) FP_HIP(hipEventRecord(l0, s));
             }
-            FP_HIP(launch_eval_kernel(h->n1, h->E, n, a, F, h->d_basis, s));
+            FP_HIP(launch_eval_kernel(h->n1, h->E, n, a, F, h->d_basis, h->d_basis32,
+                                      h->precision == FP_PREC_MIXED, s));
         }
         if (timed) {
             FP_HIP(hipEventRecord(l1, s));

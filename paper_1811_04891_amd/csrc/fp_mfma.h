@@ -55,21 +55,21 @@ struct MShape {
 // A lane's own node order: position p holds node (p + g) mod N1, so that the
 // indices the lane needs for its slot, i = 4 m + g, sit at the fixed positions
 // 4 m (weight 0 past the last node).  Loaded once per kernel.
-template <int N1>
+template <int N1, class T = double>
 struct LaneNodes {
-    double z[N1];
-    double w[MShape<N1>::KB];
+    T z[N1];
+    T w[MShape<N1>::KB];
 };
 
-template <int N1>
-__device__ __forceinline__ void lane_nodes(BasisPtr<double> B, int g, LaneNodes<N1> &Z)
+template <int N1, class T = double>
+__device__ __forceinline__ void lane_nodes(BasisPtr<double> B, int g, LaneNodes<N1, T> &Z)
 {
 #pragma unroll
-    for (int p = 0; p < N1; ++p) Z.z[p] = B.z((p + g) % N1);
+    for (int p = 0; p < N1; ++p) Z.z[p] = (T)B.z((p + g) % N1);
 #pragma unroll
     for (int m = 0; m < MShape<N1>::KB; ++m) {
         const int i = 4 * m + g;
-        Z.w[m] = i < N1 ? B.wb(i) : 0.0;
+        Z.w[m] = i < N1 ? (T)B.wb(i) : T(0);
     }
 }
 
@@ -107,17 +107,17 @@ __device__ __forceinline__ void lagrange_d_lane(const LaneNodes<N1> &Z, double r
 }
 
 // h_i(r) alone for the lane's indices i = 4 m + g (as lagrange_d_lane).
-template <int N1>
-__device__ __forceinline__ void lagrange_lane(const LaneNodes<N1> &Z, double r,
-                                              double (&h)[MShape<N1>::KB])
+template <int N1, class T = double>
+__device__ __forceinline__ void lagrange_lane(const LaneNodes<N1, T> &Z, T r,
+                                              T (&h)[MShape<N1>::KB])
 {
-    double t[N1], pl[N1], pr[N1];
+    T t[N1], pl[N1], pr[N1];
 #pragma unroll
     for (int p = 0; p < N1; ++p) t[p] = r - Z.z[p];
-    pl[0] = 1.0;
+    pl[0] = T(1);
 #pragma unroll
     for (int p = 1; p < N1; ++p) pl[p] = pl[p - 1] * t[p - 1];
-    pr[N1 - 1] = 1.0;
+    pr[N1 - 1] = T(1);
 #pragma unroll
     for (int p = N1 - 2; p >= 0; --p) pr[p] = pr[p + 1] * t[p + 1];
 #pragma unroll

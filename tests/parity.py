@@ -82,6 +82,15 @@ def compare_locate(om, pts, gpu, ora, h, tol, max_report=5, check_residual_every
             "max_dr": float(np.max(np.abs(gr[same] - orr[same]))) if np.any(same) else 0.0}
 
 
+# Mixed-precision interpolation (orders up to 7) accumulates in binary32:
+# three sum-factorised contractions of n1 <= 8 terms, each within
+# gamma_8 sum|terms| <= 8 u Lambda max|input| (u = 2^-24, Lambda = the GLL
+# Lebesgue constant, 1.97 at N = 7), plus the binary32 rounding of the nodal
+# values and of the basis values: at most (3 * 8 + 4) u Lambda^3 max|F| =
+# 1.3e-5 max|F|.
+MIXED_EVAL_REL = 2e-5
+
+
 def compare_eval(gpu_out, ref_out, fields, rel=1e-13):
     """|f_gpu - f_ref| <= rel * max|F| per field; NaN exactly where the
     reference is NaN."""

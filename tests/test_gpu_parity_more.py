@@ -22,7 +22,7 @@ import torch
 
 import oracle
 import workloads as w
-from parity import compare_eval, compare_locate
+from parity import MIXED_EVAL_REL, compare_eval, compare_locate
 
 pytestmark = pytest.mark.gpu
 
@@ -73,6 +73,36 @@ def test_eval_many_fields(dev, N, nf):
     om = oracle.OracleMesh.from_mesh(mesh, TOL)
     ref = om.eval(code, el, rst, [f.numpy() for f in fields])
     compare_eval(out.cpu().numpy(), ref, [f.numpy() for f in fields], rel=1e-13)
+    h.free()
+
+
+@pytest.mark.parametrize("N", [4, 7, 9])
+@pytest.mark.parametrize("nf", [5, 9])
+def test_eval_many_fields_mixed(dev, N, nf):
+    """Mixed precision: orders up to 7 interpolate in binary32 (binary32
+    accumulation, all fields of a launch in one pass), within MIXED_EVAL_REL
+    max|F| of the oracle; higher orders interpolate in binary64."""
+    fp = _fp()
+    _say(f"case: findpts_eval mixed N={N} nf={nf}")
+    mesh = w.annulus_mesh(2, 8, 2, N=N)
+    fields, _ = w.poly_fields(mesh, nf, seed=300 + N + nf)
+    rng = np.random.default_rng(400 + N + nf)
+    P = 20_001
+    el = np.where(rng.uniform(size=P) < 0.3, 5, rng.integers(0, mesh.E, P)).astype(np.int32)
+    rst = rng.uniform(-1, 1, (P, 3))
+    code = np.zeros(P, np.int32)
+    nf_idx = rng.choice(P, 200, replace=False)
+    code[nf_idx], el[nf_idx], rst[nf_idx] = 2, -1, 0.0
+    md = mesh.to(dev)
+    h = fp.findpts_setup(md.x, md.y, md.z, N, tol=TOL, max_points=P,
+                         precision=fp.FP_PREC_MIXED)
+    out = fp.findpts_eval(h, torch.as_tensor(code).to(dev), torch.as_tensor(el).to(dev),
+                          torch.as_tensor(rst).to(dev), [f.to(dev) for f in fields])
+    torch.cuda.synchronize()
+    om = oracle.OracleMesh.from_mesh(mesh, TOL)
+    hf = [f.numpy() for f in fields]
+    ref = om.eval(code, el, rst, hf)
+    compare_eval(out.cpu().numpy(), ref, hf, rel=MIXED_EVAL_REL if N <= 7 else 1e-13)
     h.free()
 
 
