@@ -602,9 +602,9 @@ def headline(args, fp, w, dev, head, other, pname):
         },
         "roofline": {
             "bound": "alu",
-            "kernel": ("k_locate_mfma<8> (trust-region Newton, FP64 matrix cores), first pass"
+            "kernel": ("k_newton8 (trust-region Newton, binary64 matrix cores), first pass"
                        if head == fp.FP_PREC_FP64 else
-                       "k_locate_mixed<8> (FP32 Newton + FP64 end game), first pass"),
+                       "k_mixed8 (binary32 Newton + binary64 refinement), first pass"),
             "achieved": sh["locate_tflops"],
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
