@@ -175,14 +175,16 @@ __global__ __launch_bounds__(kEvThreads) void k_eval_grp(EvArgs a, FieldPtrs F,
 // (evaluating only its own i and j, in its rotated node order), contracts its
 // rows j = g + 4 w with h_j(s) and every plane k with h_k(t), and the 4 lanes
 // of point n add their partial sums (same order in all 4: the total is
-// bit-identical).  T is the arithmetic: binary64 (4 fields per pass), or
-// binary32 with binary32 accumulation for mixed precision (all 8 fields of a
-// launch in one pass, binary32 basis and matrix products; the nodal values
-// are rounded to binary32, the result widened to binary64).
-constexpr int kEvFieldsPerPass = 4;
+// bit-identical).  T is the arithmetic: binary64, or binary32 with binary32
+// accumulation for mixed precision (binary32 basis and matrix products; the
+// nodal values are rounded to binary32, the result widened to binary64).  NF
+// fields' fragments are held per pass: 4, or all 8 of a launch when it has
+// more than 4 (one pass reads each point's r and evaluates its basis once;
+// the larger fragment set costs occupancy, so launches of up to 4 fields keep
+// the smaller one).
 constexpr int kUnitEvalMfma = 512;  // points of one element per work unit
 
-template <int N1, class T>
+template <int N1, class T, int NF>
 __global__ __launch_bounds__(kWave) void k_eval_mfma(EvArgs a, FieldPtrs F,
                                                      const double *__restrict__ basis,
                                                      const float *__restrict__ basis32)
@@ -190,7 +192,6 @@ __global__ __launch_bounds__(kWave) void k_eval_mfma(EvArgs a, FieldPtrs F,
     using S = MShape<N1>;
     constexpr int V = N1 * N1 * N1;
     constexpr int MBF = (N1 + S::PPB - 1) / S::PPB;  // M blocks per field (planes k)
-    constexpr int NF = sizeof(T) == sizeof(double) ? kEvFieldsPerPass : kMaxEvalFields;
     const BasisPtr<double> B{as_const(basis)};
     const BasisPtr<float> B32{as_const(basis32)};
     LaneNodes<N1, T> Z;  // h_i(r), h_j(s) only for the lane's own i, j = g + 4 w
@@ -268,14 +269,18 @@ __global__ __launch_bounds__(kWave) void k_eval_mfma(EvArgs a, FieldPtrs F,
 static hipError_t launch_eval_kernel(int n1, int E, int n, const EvArgs &a, const FieldPtrs &F,
                                      const double *B, const float *B32, bool mixed, hipStream_t s)
 {
-#define FP_LAUNCH_MFMA(N1)                                                              \
-    do {                                                                                \
-        if (mixed)                                                                      \
-            k_eval_mfma<N1, float><<<unit_grid(E, n, kUnitEvalMfma), kWave, 0, s>>>(a, F, B, \
-                                                                                   B32); \
-        else                                                                            \
-            k_eval_mfma<N1, double><<<unit_grid(E, n, kUnitEvalMfma), kWave, 0, s>>>(a, F, B, \
-                                                                                    B32); \
+#define FP_EVAL_MFMA(N1, T, NF) \
+    k_eval_mfma<N1, T, NF><<<unit_grid(E, n, kUnitEvalMfma), kWave, 0, s>>>(a, F, B, B32)
+#define FP_LAUNCH_MFMA(N1)                                                  \
+    do {                                                                    \
+        if (mixed && a.nf > 4)                                              \
+            FP_EVAL_MFMA(N1, float, kMaxEvalFields);                        \
+        else if (mixed)                                                     \
+            FP_EVAL_MFMA(N1, float, 4);                                     \
+        else if (a.nf > 4)                                                  \
+            FP_EVAL_MFMA(N1, double, kMaxEvalFields);                       \
+        else                                                                \
+            FP_EVAL_MFMA(N1, double, 4);                                    \
     } while (0)
     switch (n1) {
         case 2: FP_LAUNCH_MFMA(2); return hipGetLastError();
@@ -288,6 +293,7 @@ static hipError_t launch_eval_kernel(int n1, int E, int n, const EvArgs &a, cons
         default: break;
     }
 #undef FP_LAUNCH_MFMA
+#undef FP_EVAL_MFMA
 #define FP_LAUNCH_GRP(N1)                                                                 \
     k_eval_grp<N1><<<unit_grid((E + EvGroup<N1>::G - 1) / EvGroup<N1>::G, n, kUnitGrp),   \
                      kEvThreads, 0, s>>>(a, F, B)

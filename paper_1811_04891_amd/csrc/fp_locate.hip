@@ -162,6 +162,9 @@ __global__ __launch_bounds__(256) void k_cand(LocArgs a)
                         if (in == (a.only != nullptr)) continue;  // second pass: the dropped
                     }
                     ce[(long long)n * a.M] = e;
+                    // a slot appended by the second pass is new: no state of
+                    // an earlier call may read as a pair to resume
+                    if (a.only) a.res_in[(long long)n * a.M + t] = 0;
                     ++n;
                 }
                 // the method's whole set: taken in pass 1, or left intact by
@@ -303,6 +306,14 @@ struct TRNewton {
     __device__ __forceinline__ bool update(const double (&xt)[3], const double (&Jt)[9],
                                            const double (&xs)[3], double rstop)
     {
+        return accept(xt, Jt, xs, rstop) || step();
+    }
+
+    // The two halves of update.  accept: take or reject the trial point rt
+    // (model ratio, radius) and test the stop rules; true when done.
+    __device__ __forceinline__ bool accept(const double (&xt)[3], const double (&Jt)[9],
+                                           const double (&xs)[3], double rstop)
+    {
         const double Ft[3] = {xt[0] - xs[0], xt[1] - xs[1], xt[2] - xs[2]};
         const double phit = fma(Ft[2], Ft[2], fma(Ft[1], Ft[1], Ft[0] * Ft[0]));
         bool acc = true, stop = false;
@@ -329,7 +340,13 @@ struct TRNewton {
         for (int d = 0; d < 9; ++d) J[d] = acc ? Jt[d] : J[d];
         phi = acc ? phit : phi;
         have = true;
-        if (stop || phi <= rstop || it >= max_it) return true;
+        return stop || phi <= rstop || it >= max_it;
+    }
+
+    // step: the next trial point rt from the accepted state; true when no
+    // step can be taken (the pair is then done).
+    __device__ __forceinline__ bool step()
+    {
         ++it;
         double g[3];
 #pragma unroll
