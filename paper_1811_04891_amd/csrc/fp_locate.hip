@@ -565,6 +565,7 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
 #include "fp_mfma.inc"
 #include "fp_newton8.inc"
 #include "fp_mixed8.inc"
+#include "fp_newton_pl.inc"
 
 constexpr int kStatsBlocks = 32;
 
@@ -759,6 +760,13 @@ static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, int
             k_locate_mfma<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_dnode);     \
         }                                                                            \
     } while (0)
+// orders 8 and 9: binary64 matrix cores, one plane per lane, in both
+// precisions (no binary32 phase at these orders)
+#define FP_LAUNCH_PL(N1)                                                   \
+    do {                                                                   \
+        *nblk = FP_GRID(kUnitMfma);                                        \
+        k_newton_pl<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_dnode);     \
+    } while (0)
     switch (h->n1) {
         case 2: FP_LAUNCH_MFMA(2); break;
         case 3: FP_LAUNCH_MFMA(3); break;
@@ -767,8 +775,8 @@ static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, int
         case 6: FP_LAUNCH_MFMA(6); break;
         case 7: FP_LAUNCH_MFMA(7); break;
         case 8: FP_LAUNCH_MFMA(8); break;
-        case 9: FP_LAUNCH_LOCATE(9); break;
-        case 10: FP_LAUNCH_LOCATE(10); break;
+        case 9: FP_LAUNCH_PL(9); break;
+        case 10: FP_LAUNCH_PL(10); break;
         case 11: FP_LAUNCH_LOCATE(11); break;
         case 12: FP_LAUNCH_LOCATE(12); break;
         case 13: FP_LAUNCH_LOCATE(13); break;
@@ -779,6 +787,7 @@ static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, int
     }
 #undef FP_LAUNCH_LOCATE
 #undef FP_LAUNCH_MFMA
+#undef FP_LAUNCH_PL
 #undef FP_GRID
     return hipGetLastError();
 }

@@ -48,8 +48,8 @@ def served(dev):
     return ms, handles
 
 
-def _requests(ms, n, seed, p_max=30_000):
-    rq = w.serving_requests(n, len(ms), p_min=1, p_max=p_max, nf_max=3, seed=seed)
+def _requests(ms, n, seed, p_max=30_000, p_min=1):
+    rq = w.serving_requests(n, len(ms), p_min=p_min, p_max=p_max, nf_max=3, seed=seed)
     rng = np.random.default_rng(seed)
     for r in rq:
         if rng.random() < 0.2:
@@ -126,8 +126,10 @@ def test_serving_small_budget_waits(dev, served):
     fp = _fp()
     ms, handles = served
     _say("case: HBM budget of about one request workspace: admission waits")
-    # the workspace of the largest request alone (one pass), plus a little
-    rq = _requests(ms, 24, seed=42, p_max=20_000)
+    # the workspace of the largest request alone (one pass), plus a little;
+    # requests of 50,000..200,000 points run longer on the GPU than the host
+    # takes to submit the next, so their workspaces would overlap in time
+    rq = _requests(ms, 24, seed=42, p_max=200_000, p_min=50_000)
     big = max(rq, key=lambda r: r["P"])
     probe = fp.Server(1 << 30, slots=1)
     pid = [probe.add_mesh(h, m.fields) for h, m in zip(handles, ms)]
