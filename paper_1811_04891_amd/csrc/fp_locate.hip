@@ -765,7 +765,7 @@ static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, int
 #define FP_LAUNCH_PL(N1)                                                   \
     do {                                                                   \
         *nblk = FP_GRID(kUnitMfma);                                        \
-        k_newton_pl<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_dnode);     \
+        k_newton_pl<N1><<<*nblk, 2 * kWave, 0, s>>>(a, h->d_basis, h->d_dnode);  \
     } while (0)
     switch (h->n1) {
         case 2: FP_LAUNCH_MFMA(2); break;
