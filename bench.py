@@ -57,9 +57,8 @@ def eval_flops_per_point(N, nf):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("fp_locate.hip", "fp_mfma.inc", "fp_newton8.inc", "fp_mixed8.inc", "fp_mfma.h",
-              "fp_basis.h",
-              "fp_internal.h"):
+    for f in ("fp_locate.hip", "fp_mfma.inc", "fp_newton8.inc", "fp_mixed8.inc",
+              "fp_newton_pl.inc", "fp_mfma.h", "fp_basis.h", "fp_internal.h"):
         with open(os.path.join(ROOT, "paper_1811_04891_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -760,12 +760,18 @@ static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, int
             k_locate_mfma<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_dnode);     \
         }                                                                            \
     } while (0)
-// orders 8 and 9: binary64 matrix cores, one plane per lane, in both
-// precisions (no binary32 phase at these orders)
-#define FP_LAUNCH_PL(N1)                                                   \
-    do {                                                                   \
-        *nblk = FP_GRID(kUnitMfma);                                        \
-        k_newton_pl<N1><<<*nblk, 2 * kWave, 0, s>>>(a, h->d_basis, h->d_dnode);  \
+// orders 8 and 9: matrix cores, one plane per lane; mixed precision (first
+// pass): a binary32 phase, then binary64 Newton from its end points
+#define FP_LAUNCH_PL(N1)                                                              \
+    do {                                                                              \
+        *nblk = FP_GRID(kUnitMfma);                                                   \
+        if (h->precision == FP_PREC_MIXED && a.obb) {                                 \
+            k_mixed_pl<N1><<<*nblk, 2 * kWave, 0, s>>>(a, h->d_basis32, h->d_dnode); \
+            k_newton_pl<N1, true><<<*nblk, 2 * kWave, 0, s>>>(a, h->d_basis, h->d_basis32, \
+                                                             h->d_dnode);             \
+        } else                                                                        \
+            k_newton_pl<N1, false><<<*nblk, 2 * kWave, 0, s>>>(a, h->d_basis, h->d_basis32, \
+                                                              h->d_dnode);            \
     } while (0)
     switch (h->n1) {
         case 2: FP_LAUNCH_MFMA(2); break;

@@ -76,23 +76,23 @@ __device__ __forceinline__ void lane_nodes(BasisPtr<double> B, int g, LaneNodes<
 // h_i(r) and h_i'(r) for the lane's indices i = 4 m + g: the product of
 // (r - z) over the other nodes, taken in the lane's node order (prefix times
 // suffix products), so no lane computes the basis functions it does not use.
-template <int N1>
-__device__ __forceinline__ void lagrange_d_lane(const LaneNodes<N1> &Z, double r,
-                                                double (&h)[MShape<N1>::KB],
-                                                double (&d)[MShape<N1>::KB])
+template <int N1, class T = double>
+__device__ __forceinline__ void lagrange_d_lane(const LaneNodes<N1, T> &Z, T r,
+                                                T (&h)[MShape<N1>::KB],
+                                                T (&d)[MShape<N1>::KB])
 {
-    double t[N1], pl[N1], dpl[N1], pr[N1], dpr[N1];
+    T t[N1], pl[N1], dpl[N1], pr[N1], dpr[N1];
 #pragma unroll
     for (int p = 0; p < N1; ++p) t[p] = r - Z.z[p];
-    pl[0] = 1.0;
-    dpl[0] = 0.0;
+    pl[0] = T(1);
+    dpl[0] = T(0);
 #pragma unroll
     for (int p = 1; p < N1; ++p) {
         dpl[p] = dpl[p - 1] * t[p - 1] + pl[p - 1];
         pl[p] = pl[p - 1] * t[p - 1];
     }
-    pr[N1 - 1] = 1.0;
-    dpr[N1 - 1] = 0.0;
+    pr[N1 - 1] = T(1);
+    dpr[N1 - 1] = T(0);
 #pragma unroll
     for (int p = N1 - 2; p >= 0; --p) {
         dpr[p] = dpr[p + 1] * t[p + 1] + pr[p + 1];

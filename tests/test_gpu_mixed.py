@@ -119,7 +119,7 @@ def test_mixed_vs_fp64_full_size(dev, c2):
     _say(f"mixed full ok: {int(np.sum(ties))} face ties vs fp64; sample {st}")
 
 
-@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_mixed_orders(dev, N):
     fp = _fp()
     _say(f"case: mixed precision, order N={N}")
@@ -134,6 +134,25 @@ def test_mixed_orders(dev, N):
         pts = np.stack([rho * np.cos(th), rho * np.sin(th), rng.uniform(-0.05, 1.05, 3000)], 1)
     else:
         pts = rng.uniform((-1.1, -0.1, -0.1), (2.1, 1.1, 0.6), (3000, 3))
+    pts = torch.as_tensor(pts)
+    h, g, _ = _run(fp, mesh, pts, dev, fp.FP_PREC_MIXED)
+    om = oracle.OracleMesh.from_mesh(mesh, TOL)
+    _, hs = om.bbox()
+    compare_locate(om, pts.numpy(), g, om.findpts(pts.numpy()), hs, TOL)
+
+
+@pytest.mark.parametrize("N", [8, 9])
+def test_mixed_high_order_many_chunks(dev, N):
+    """Orders 8 and 9 (a binary32 launch, then binary64 Newton from its end
+    points): 4 curved elements with 3000 points, so each element's pairs span
+    several pair chunks of both kernels and many 16-slot rounds."""
+    fp = _fp()
+    _say(f"case: mixed precision, order N={N}, 4 elements x 750 points")
+    mesh = w.annulus_mesh(1, 4, 1, N=N)
+    rng = np.random.default_rng(60 + N)
+    rho = np.sqrt(rng.uniform(0.2, 1.2, 3000))
+    th = rng.uniform(0, 2 * np.pi, 3000)
+    pts = np.stack([rho * np.cos(th), rho * np.sin(th), rng.uniform(-0.05, 1.05, 3000)], 1)
     pts = torch.as_tensor(pts)
     h, g, _ = _run(fp, mesh, pts, dev, fp.FP_PREC_MIXED)
     om = oracle.OracleMesh.from_mesh(mesh, TOL)
