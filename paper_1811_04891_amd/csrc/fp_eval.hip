@@ -32,6 +32,10 @@ struct EvArgs {
     int nf;
     double *out_all;  // first field of the call, for NaN fill
     int nf_all;
+    double *sink;     // kEvSink doubles that nothing reads
+    double *stage;    // non-null: k_eval_mfma writes the value of field f at list
+                      // position u to stage[u * nf + f], and k_ev_unstage moves
+                      // it to out (else it writes out directly)
 };
 
 // Count points per element; not-found points get NaN right away.
@@ -56,6 +60,20 @@ __global__ __launch_bounds__(256) void k_ev_scatter(EvArgs a)
     if (p >= a.npts) return;
     const int k = a.pos[p];
     if (k >= 0) a.order[a.off[a.el[p]] + k] = p;
+}
+
+// Staged values to the caller's field-major output: each point reads its nf
+// values (one run of nf doubles at its place in the element-grouped list) and
+// the stores of consecutive points are consecutive.  Not-found points were
+// filled with NaN by k_ev_count.
+__global__ __launch_bounds__(256) void k_ev_unstage(EvArgs a)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.npts) return;
+    const int k = a.pos[p];
+    if (k < 0) return;
+    const double *src = a.stage + (long long)(a.off[a.el[p]] + k) * a.nf;
+    for (int f = 0; f < a.nf; ++f) a.out[f * a.ostride + p] = src[f];
 }
 
 // One wavefront per work unit: up to kUnitEval points of one element, 64 at a
@@ -178,11 +196,11 @@ __global__ __launch_bounds__(kEvThreads) void k_eval_grp(EvArgs a, FieldPtrs F,
 // bit-identical).  T is the arithmetic: binary64, or binary32 with binary32
 // accumulation for mixed precision (binary32 basis and matrix products; the
 // nodal values are rounded to binary32, the result widened to binary64).  NF
-// fields' fragments are held per pass: 4, or all 8 of a launch when it has
-// more than 4 (one pass reads each point's r and evaluates its basis once;
-// the larger fragment set costs occupancy, so launches of up to 4 fields keep
-// the smaller one).
+// is the launch's field count (at most 8), so one pass reads each point's r
+// and evaluates its basis once for all fields, and no register holds the
+// fragments of a field the launch does not have.
 constexpr int kUnitEvalMfma = 512;  // points of one element per work unit
+constexpr int kEvMfmaMaxN1 = 8;      // orders with the matrix-core kernel
 
 template <int N1, class T, int NF>
 __global__ __launch_bounds__(kWave) void k_eval_mfma(EvArgs a, FieldPtrs F,
@@ -206,60 +224,77 @@ __global__ __launch_bounds__(kWave) void k_eval_mfma(EvArgs a, FieldPtrs F,
         const int row = lane & 15, q = lane >> 4;
         const int gr = MF<T>::grp(row), vr = MF<T>::comp(row);
         const int pr = vr / S::EPP, jj = gr + 4 * (vr % S::EPP);
-        for (int f0 = 0; f0 < a.nf; f0 += NF) {
-            T A[NF][MBF][S::KB];
-    #pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                const double *src = (f0 + f < a.nf) ? F.f[f0 + f] + (long long)e * V : nullptr;
-    #pragma unroll
-                for (int mb = 0; mb < MBF; ++mb) {
-                    const int k = mb * S::PPB + pr;
-    #pragma unroll
-                    for (int kb = 0; kb < S::KB; ++kb) {
-                        const int i = 4 * kb + q;
-                        const bool ok = src && k < N1 && jj < N1 && i < N1;
-                        A[f][mb][kb] = ok ? (T)src[N1 * (jj + N1 * k) + i] : T(0);
-                    }
+        T A[NF][MBF][S::KB];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const double *src = F.f[f] + (long long)e * V;
+#pragma unroll
+            for (int mb = 0; mb < MBF; ++mb) {
+                const int k = mb * S::PPB + pr;
+#pragma unroll
+                for (int kb = 0; kb < S::KB; ++kb) {
+                    const int i = 4 * kb + q;
+                    const bool ok = k < N1 && jj < N1 && i < N1;
+                    A[f][mb][kb] = ok ? (T)src[N1 * (jj + N1 * k) + i] : T(0);
                 }
             }
-            for (int b0 = beg; b0 < end; b0 += 16) {
-                const int u = b0 + n;
-                const bool act = u < end;
-                const int p = a.order[act ? u : beg];
-                static_assert(S::KB == S::EPP, "r and s rows use the same lane indices");
-                T hrl[S::KB], hsl[S::EPP], ht[N1];
-                lagrange_lane<N1, T>(Z, (T)a.rst[3 * (long long)p], hrl);
-                lagrange_lane<N1, T>(Z, (T)a.rst[3 * (long long)p + 1], hsl);
-                if constexpr (sizeof(T) == sizeof(double))
-                    lagrange<N1>(B, a.rst[3 * (long long)p + 2], ht);
-                else
-                    lagrange<N1>(B32, (float)a.rst[3 * (long long)p + 2], ht);
-    #pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    if (f0 + f < a.nf) {
-                        T v = 0;
-    #pragma unroll
-                        for (int mb = 0; mb < MBF; ++mb) {
-                            typename MF<T>::acc c = {0, 0, 0, 0};
-    #pragma unroll
-                            for (int kb = 0; kb < S::KB; ++kb)
-                                c = MF<T>::mma(A[f][mb][kb], hrl[kb], c);
-    #pragma unroll
-                            for (int pp = 0; pp < S::PPB; ++pp) {
-                                const int k = mb * S::PPB + pp;
-                                if (k < N1) {
-                                    T sa = 0;
-    #pragma unroll
-                                    for (int w = 0; w < S::EPP; ++w)
-                                        sa = fma(c[pp * S::EPP + w], hsl[w], sa);
-                                    v = fma(sa, ht[k], v);
-                                }
-                            }
+        }
+        // Software pipeline over the batches of 16 points: the point ids of
+        // batch b + 2 and the r of batch b + 1 are in flight while batch b
+        // computes.  The loop body has no branch: loads past the unit read
+        // its first point again, and the slots past the unit store into the
+        // sink, so the wait for the next batch's r counts only the memory
+        // operations issued after it and never waits for this batch's stores.
+        const auto pid = [&](int u) { return a.order[u < end ? u : beg]; };
+        int p_next = pid(beg + n);
+        double r_next[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) r_next[d] = a.rst[3 * (long long)p_next + d];
+        int p_after = pid(beg + 16 + n);
+        for (int b0 = beg; b0 < end; b0 += 16) {
+            const bool act = b0 + n < end;
+            const int p = p_next;
+            const double r0 = r_next[0], r1 = r_next[1], r2 = r_next[2];
+            p_next = p_after;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) r_next[d] = a.rst[3 * (long long)p_next + d];
+            p_after = pid(b0 + 32 + n);
+            static_assert(S::KB == S::EPP, "r and s rows use the same lane indices");
+            T hrl[S::KB], hsl[S::EPP], ht[N1];
+            lagrange_lane<N1, T>(Z, (T)r0, hrl);
+            lagrange_lane<N1, T>(Z, (T)r1, hsl);
+            if constexpr (sizeof(T) == sizeof(double))
+                lagrange<N1>(B, r2, ht);
+            else
+                lagrange<N1>(B32, (float)r2, ht);
+            // the 4 lanes of a slot hold bit-identical totals and all store
+            // them (to the staging list, or to the caller's output); the
+            // slots past the unit store into the sink
+            const long long fs = a.stage ? 1 : a.ostride;
+            double *dst = !act     ? a.sink + ((unit * 16 + n) & (kEvSink - 1))
+                          : a.stage ? a.stage + (long long)(b0 + n) * NF
+                                    : a.out + p;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                T v = 0;
+#pragma unroll
+                for (int mb = 0; mb < MBF; ++mb) {
+                    typename MF<T>::acc c = {0, 0, 0, 0};
+#pragma unroll
+                    for (int kb = 0; kb < S::KB; ++kb) c = MF<T>::mma(A[f][mb][kb], hrl[kb], c);
+#pragma unroll
+                    for (int pp = 0; pp < S::PPB; ++pp) {
+                        const int k = mb * S::PPB + pp;
+                        if (k < N1) {
+                            T sa = 0;
+#pragma unroll
+                            for (int w = 0; w < S::EPP; ++w) sa = fma(c[pp * S::EPP + w], hsl[w], sa);
+                            v = fma(sa, ht[k], v);
                         }
-                        v = slot_sum(v);
-                        if (act && g == 0) a.out[(f0 + f) * a.ostride + p] = (double)v;
                     }
                 }
+                v = slot_sum(v);
+                dst[act ? f * fs : 0] = (double)v;
             }
         }
     }
@@ -271,16 +306,25 @@ static hipError_t launch_eval_kernel(int n1, int E, int n, const EvArgs &a, cons
 {
 #define FP_EVAL_MFMA(N1, T, NF) \
     k_eval_mfma<N1, T, NF><<<unit_grid(E, n, kUnitEvalMfma), kWave, 0, s>>>(a, F, B, B32)
-#define FP_LAUNCH_MFMA(N1)                                                  \
-    do {                                                                    \
-        if (mixed && a.nf > 4)                                              \
-            FP_EVAL_MFMA(N1, float, kMaxEvalFields);                        \
-        else if (mixed)                                                     \
-            FP_EVAL_MFMA(N1, float, 4);                                     \
-        else if (a.nf > 4)                                                  \
-            FP_EVAL_MFMA(N1, double, kMaxEvalFields);                       \
-        else                                                                \
-            FP_EVAL_MFMA(N1, double, 4);                                    \
+#define FP_EVAL_NF(N1, T)                   \
+    do {                                    \
+        switch (a.nf) {                     \
+            case 1: FP_EVAL_MFMA(N1, T, 1); break; \
+            case 2: FP_EVAL_MFMA(N1, T, 2); break; \
+            case 3: FP_EVAL_MFMA(N1, T, 3); break; \
+            case 4: FP_EVAL_MFMA(N1, T, 4); break; \
+            case 5: FP_EVAL_MFMA(N1, T, 5); break; \
+            case 6: FP_EVAL_MFMA(N1, T, 6); break; \
+            case 7: FP_EVAL_MFMA(N1, T, 7); break; \
+            default: FP_EVAL_MFMA(N1, T, 8); break; \
+        }                                   \
+    } while (0)
+#define FP_LAUNCH_MFMA(N1)             \
+    do {                               \
+        if (mixed)                     \
+            FP_EVAL_NF(N1, float);     \
+        else                           \
+            FP_EVAL_NF(N1, double);    \
     } while (0)
     switch (n1) {
         case 2: FP_LAUNCH_MFMA(2); return hipGetLastError();
@@ -293,6 +337,7 @@ static hipError_t launch_eval_kernel(int n1, int E, int n, const EvArgs &a, cons
         default: break;
     }
 #undef FP_LAUNCH_MFMA
+#undef FP_EVAL_NF
 #undef FP_EVAL_MFMA
 #define FP_LAUNCH_GRP(N1)                                                                 \
     k_eval_grp<N1><<<unit_grid((E + EvGroup<N1>::G - 1) / EvGroup<N1>::G, n, kUnitGrp),   \
@@ -357,6 +402,7 @@ int run_eval(fp_handle *h, const Work &w, int npts, const int *code, const int *
             a.nf = nf;
             a.out_all = out + start;
             a.nf_all = nfields;
+            a.sink = w.ev_sink;
             FieldPtrs F{};
             for (int f = 0; f < nf; ++f) F.f[f] = h_fields[f0 + f];
             const int pb = (n + 255) / 256;
@@ -369,8 +415,20 @@ int run_eval(fp_handle *h, const Work &w, int npts, const int *code, const int *
                 FP_HIP(hipGetLastError());
                 if (timed) FP_HIP(hipEventRecord(l0, s));
             }
+            // the matrix-core kernel stages its values in element order in the
+            // pair-results array of the workspace (dead once findpts has
+            // returned); without that array (the allocation-free entry) or
+            // room for it, it writes the output directly
+            a.stage = (h->n1 <= kEvMfmaMaxN1 && w.res &&
+                       (long long)n * nf <= (long long)w.M * w.MC * 4)
+                          ? w.res
+                          : nullptr;
             FP_HIP(launch_eval_kernel(h->n1, h->E, n, a, F, h->d_basis, h->d_basis32,
                                       h->precision == FP_PREC_MIXED, s));
+            if (a.stage) {
+                k_ev_unstage<<<pb, 256, 0, s>>>(a);
+                FP_HIP(hipGetLastError());
+            }
         }
         if (timed) {
             FP_HIP(hipEventRecord(l1, s));
@@ -428,7 +486,8 @@ static bool scratch_carve(char *base, int E, int npts, Work &w)
 {
     const size_t e1 = (size_t)E + 1;
     const size_t fixed = 2 * round256(e1 * sizeof(int)) +
-                         round256((size_t)scan_tmp_size((long long)E + 1) * sizeof(int));
+                         round256((size_t)scan_tmp_size((long long)E + 1) * sizeof(int)) +
+                         round256(kEvSink * sizeof(double));
     if (fixed >= kScratchBytes) return false;
     const size_t per = (kScratchBytes - fixed) / 2 / 256 * 256 / sizeof(int);  // ints per array
     if (per < (size_t)kScratchMinPass) return false;
@@ -443,6 +502,8 @@ static bool scratch_carve(char *base, int E, int npts, Work &w)
     q += round256(e1 * sizeof(int));
     w.scan_tmp = (int *)q;
     q += round256((size_t)scan_tmp_size((long long)E + 1) * sizeof(int));
+    w.ev_sink = (double *)q;
+    q += round256(kEvSink * sizeof(double));
     w.ev_pos = (int *)q;
     q += per * sizeof(int);
     w.ev_order = (int *)q;

@@ -14,6 +14,7 @@ namespace fp {
 
 constexpr int kMaxN1 = 16;       // N <= 15
 constexpr int kMaxEvalFields = 8; // fields per interpolation launch
+constexpr int kEvSink = 512;       // doubles in Work::ev_sink (a power of two)
 constexpr int kStats = 6;          // device counters of a handle (findpts_stats)
 constexpr int kTimedPhases = 5;    // timed phases (findpts_timing_read)
 constexpr int kWave = 64;
@@ -68,6 +69,7 @@ struct Work {
     int *ev_off = nullptr;    // E + 1
     int *ev_pos = nullptr;    // M
     int *ev_order = nullptr;  // M
+    double *ev_sink = nullptr;  // kEvSink: stores of interpolation slots past a unit
 };
 
 // Bytes of a workspace (256-byte aligned sub-arrays); carve() lays it out
