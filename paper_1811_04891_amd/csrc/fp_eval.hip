@@ -8,6 +8,7 @@
 #include <mutex>
 
 #include "fp_basis.h"
+#include "fp_group.h"
 #include "fp_internal.h"
 #include "fp_mfma.h"
 
@@ -33,9 +34,21 @@ struct EvArgs {
     double *out_all;  // first field of the call, for NaN fill
     int nf_all;
     double *sink;     // kEvSink doubles that nothing reads
-    double *stage;    // non-null: k_eval_mfma writes the value of field f at list
-                      // position u to stage[u * nf + f], and k_ev_unstage moves
-                      // it to out (else it writes out directly)
+    double *stage;     // non-null: k_eval_mfma writes the value of field f of the
+                       // point at list position u to stage[slot[u] * nf + f], and
+                       // k_ev_unstage moves it to out (else it writes out directly)
+    const int *slot;   // stage row of each list position (order when not staged)
+};
+
+// Grouping key of a point: its element, or -1 when it was not found.
+struct EvKey {
+    const int *code, *el;
+    int E;
+    __device__ __forceinline__ int operator()(int p) const
+    {
+        const int e = el[p];
+        return (code[p] != FP_NOT_FOUND && e >= 0 && e < E) ? e : -1;
+    }
 };
 
 // Count points per element; not-found points get NaN right away.
@@ -63,16 +76,21 @@ __global__ __launch_bounds__(256) void k_ev_scatter(EvArgs a)
 }
 
 // Staged values to the caller's field-major output: each point reads its nf
-// values (one run of nf doubles at its place in the element-grouped list) and
-// the stores of consecutive points are consecutive.  Not-found points were
-// filled with NaN by k_ev_count.
+// values (its stage row is its index in the grouping's bucket order, so the
+// rows of a grouping tile's points lie in a few runs) and the stores of
+// consecutive points are consecutive.  Points that were not found get NaN.
 __global__ __launch_bounds__(256) void k_ev_unstage(EvArgs a)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    // the blocks of one grouping tile run on one die, whose L2 then holds
+    // the tile's runs of stage rows
+    const int p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (p >= a.npts) return;
-    const int k = a.pos[p];
-    if (k < 0) return;
-    const double *src = a.stage + (long long)(a.off[a.el[p]] + k) * a.nf;
+    const int j = a.pos[p];
+    if (j < 0) {
+        for (int f = 0; f < a.nf; ++f) a.out[f * a.ostride + p] = NAN;
+        return;
+    }
+    const double *src = a.stage + (long long)j * a.nf;
     for (int f = 0; f < a.nf; ++f) a.out[f * a.ostride + p] = src[f];
 }
 
@@ -201,9 +219,16 @@ __global__ __launch_bounds__(kEvThreads) void k_eval_grp(EvArgs a, FieldPtrs F,
 // fragments of a field the launch does not have.
 constexpr int kUnitEvalMfma = 512;  // points of one element per work unit
 constexpr int kEvMfmaMaxN1 = 8;      // orders with the matrix-core kernel
+// Wavefronts per SIMD the binary64 interpolation kernel with up to 5 fields
+// is held to: three (at most 168 registers; a few bytes of spills at order 7
+// with 5 fields, 12 % faster than two wavefronts on the large box); the
+// other instances take what their registers allow.
+template <class T, int NF>
+constexpr int kEvMfmaWaves = (sizeof(T) == sizeof(double) && NF <= 5) ? 3 : 1;
 
 template <int N1, class T, int NF>
-__global__ __launch_bounds__(kWave) void k_eval_mfma(EvArgs a, FieldPtrs F,
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(kEvMfmaWaves<T, NF>)))
+void k_eval_mfma(EvArgs a, FieldPtrs F,
                                                      const double *__restrict__ basis,
                                                      const float *__restrict__ basis32)
 {
@@ -245,20 +270,22 @@ __global__ __launch_bounds__(kWave) void k_eval_mfma(EvArgs a, FieldPtrs F,
         // its first point again, and the slots past the unit store into the
         // sink, so the wait for the next batch's r counts only the memory
         // operations issued after it and never waits for this batch's stores.
-        const auto pid = [&](int u) { return a.order[u < end ? u : beg]; };
-        int p_next = pid(beg + n);
+        const auto at = [&](int u) { return u < end ? u : beg; };
+        int p_next = a.order[at(beg + n)], j_next = a.slot[at(beg + n)];
         double r_next[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) r_next[d] = a.rst[3 * (long long)p_next + d];
-        int p_after = pid(beg + 16 + n);
+        int p_after = a.order[at(beg + 16 + n)], j_after = a.slot[at(beg + 16 + n)];
         for (int b0 = beg; b0 < end; b0 += 16) {
             const bool act = b0 + n < end;
-            const int p = p_next;
+            const int p = p_next, j = j_next;
             const double r0 = r_next[0], r1 = r_next[1], r2 = r_next[2];
             p_next = p_after;
+            j_next = j_after;
 #pragma unroll
             for (int d = 0; d < 3; ++d) r_next[d] = a.rst[3 * (long long)p_next + d];
-            p_after = pid(b0 + 32 + n);
+            p_after = a.order[at(b0 + 32 + n)];
+            j_after = a.slot[at(b0 + 32 + n)];
             static_assert(S::KB == S::EPP, "r and s rows use the same lane indices");
             T hrl[S::KB], hsl[S::EPP], ht[N1];
             lagrange_lane<N1, T>(Z, (T)r0, hrl);
@@ -272,7 +299,7 @@ __global__ __launch_bounds__(kWave) void k_eval_mfma(EvArgs a, FieldPtrs F,
             // slots past the unit store into the sink
             const long long fs = a.stage ? 1 : a.ostride;
             double *dst = !act     ? a.sink + ((unit * 16 + n) & (kEvSink - 1))
-                          : a.stage ? a.stage + (long long)(b0 + n) * NF
+                          : a.stage ? a.stage + (long long)j * NF
                                     : a.out + p;
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
@@ -375,6 +402,7 @@ int run_eval(fp_handle *h, const Work &w, int npts, const int *code, const int *
              const double *rst, int nfields, const double *const *h_fields, double *out,
              hipStream_t s, bool timed)
 {
+    const size_t res_bytes = w.res ? (size_t)w.M * w.MC * 4 * sizeof(double) : 0;
     for (int start = 0; start < npts; start += w.M) {
         const int n = (npts - start < w.M) ? npts - start : w.M;
         hipEvent_t t0 = nullptr, t1 = nullptr, l0 = nullptr, l1 = nullptr;
@@ -385,6 +413,19 @@ int run_eval(fp_handle *h, const Work &w, int npts, const int *code, const int *
             l1 = pool_event(h);
             FP_HIP(hipEventRecord(t0, s));
         }
+        // Staged path (matrix-core orders): points grouped by element with the
+        // two-level counting sort, values staged in the grouping's bucket
+        // order and moved to the output by k_ev_unstage.  The grouping's
+        // transient arrays and the staged values live in the pair-results
+        // array of the workspace, dead once findpts has returned.  Without
+        // that array (the allocation-free entry) or room in it: per-element
+        // counters with atomic ranks, values written to the output directly.
+        bool plan_ok = false;
+        const GroupPlan gp = group_plan(n, h->E, &plan_ok);
+        const int nf_max = nfields < kMaxEvalFields ? nfields : kMaxEvalFields;
+        const bool staged = h->n1 <= kEvMfmaMaxN1 && plan_ok && w.ev_slot &&
+                            res_bytes >= group_transient_bytes(gp) &&
+                            res_bytes >= (size_t)n * nf_max * sizeof(double);
         for (int f0 = 0; f0 < nfields; f0 += kMaxEvalFields) {
             const int nf = (nfields - f0 < kMaxEvalFields) ? nfields - f0 : kMaxEvalFields;
             EvArgs a{};
@@ -403,29 +444,33 @@ int run_eval(fp_handle *h, const Work &w, int npts, const int *code, const int *
             a.out_all = out + start;
             a.nf_all = nfields;
             a.sink = w.ev_sink;
+            a.stage = staged ? w.res : nullptr;
+            a.slot = staged ? w.ev_slot : w.ev_order;
             FieldPtrs F{};
             for (int f = 0; f < nf; ++f) F.f[f] = h_fields[f0 + f];
             const int pb = (n + 255) / 256;
             if (f0 == 0) {
-                FP_HIP(fill_int(w.ev_cnt, 0, (long long)h->E + 1, s));
-                k_ev_count<<<pb, 256, 0, s>>>(a);
-                FP_HIP(hipGetLastError());
-                FP_HIP(scan_exclusive(w.ev_cnt, w.ev_off, h->E, w.scan_tmp, s));
-                k_ev_scatter<<<pb, 256, 0, s>>>(a);
-                FP_HIP(hipGetLastError());
+                if (staged) {
+                    GroupBufs gb;
+                    gb.off = w.ev_off;
+                    gb.order = w.ev_order;
+                    gb.slot = w.ev_slot;
+                    gb.posb = w.ev_pos;
+                    group_carve(gp, (char *)w.res, gb);
+                    FP_HIP(group_by_key(EvKey{a.code, a.el, h->E}, gp, gb, s));
+                } else {
+                    FP_HIP(fill_int(w.ev_cnt, 0, (long long)h->E + 1, s));
+                    k_ev_count<<<pb, 256, 0, s>>>(a);
+                    FP_HIP(hipGetLastError());
+                    FP_HIP(scan_exclusive(w.ev_cnt, w.ev_off, h->E, w.scan_tmp, s));
+                    k_ev_scatter<<<pb, 256, 0, s>>>(a);
+                    FP_HIP(hipGetLastError());
+                }
                 if (timed) FP_HIP(hipEventRecord(l0, s));
             }
-            // the matrix-core kernel stages its values in element order in the
-            // pair-results array of the workspace (dead once findpts has
-            // returned); without that array (the allocation-free entry) or
-            // room for it, it writes the output directly
-            a.stage = (h->n1 <= kEvMfmaMaxN1 && w.res &&
-                       (long long)n * nf <= (long long)w.M * w.MC * 4)
-                          ? w.res
-                          : nullptr;
             FP_HIP(launch_eval_kernel(h->n1, h->E, n, a, F, h->d_basis, h->d_basis32,
                                       h->precision == FP_PREC_MIXED, s));
-            if (a.stage) {
+            if (staged) {
                 k_ev_unstage<<<pb, 256, 0, s>>>(a);
                 FP_HIP(hipGetLastError());
             }

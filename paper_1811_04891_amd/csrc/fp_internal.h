@@ -18,6 +18,17 @@ constexpr int kEvSink = 512;       // doubles in Work::ev_sink (a power of two)
 constexpr int kStats = 6;          // device counters of a handle (findpts_stats)
 constexpr int kTimedPhases = 5;    // timed phases (findpts_timing_read)
 constexpr int kWave = 64;
+constexpr int kXcds = 8;  // accelerator dies; workgroups are dealt to them in turn
+
+// Block index remapped so that each accelerator die (XCD, own L2) runs one
+// contiguous range of the G block indices: workgroup b is dispatched to die
+// b mod kXcds, and becomes number b / kXcds of that die's range.  A bijection
+// of [0, G); neighbouring work then shares one L2.
+__device__ __forceinline__ int xcd_block(int b, int G)
+{
+    const int x = b % kXcds, i = b / kXcds, q = G / kXcds, r = G % kXcds;
+    return x * q + (x < r ? x : r) + i;
+}
 
 // GLL nodes z_i and barycentric weights wb_i = 1 / prod_{m != i} (z_i - z_m),
 // passed to kernels by value (kernel arguments are read through the scalar
@@ -69,6 +80,7 @@ struct Work {
     int *ev_off = nullptr;    // E + 1
     int *ev_pos = nullptr;    // M
     int *ev_order = nullptr;  // M
+    int *ev_slot = nullptr;   // M: stage row of each list position (grouped path)
     double *ev_sink = nullptr;  // kEvSink: stores of interpolation slots past a unit
 };
 

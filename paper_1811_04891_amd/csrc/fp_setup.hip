@@ -528,6 +528,7 @@ void lay_out(Layout &L, Work &w, int E, int MC, int M, bool delta)
     w.ev_off = L.take<int>(e1);
     w.ev_pos = L.take<int>(m);
     w.ev_order = L.take<int>(m);
+    w.ev_slot = L.take<int>(m);
     w.ev_sink = L.take<double>(kEvSink);
 }
 }  // namespace
