@@ -219,6 +219,9 @@ __global__ __launch_bounds__(kEvThreads) void k_eval_grp(EvArgs a, FieldPtrs F,
 // fragments of a field the launch does not have.
 constexpr int kUnitEvalMfma = 512;  // points of one element per work unit
 constexpr int kEvMfmaMaxN1 = 8;      // orders with the matrix-core kernel
+// Smallest pass that takes the staged path: below it the grouping's launches
+// cost more than the scattered stores they avoid.
+constexpr int kEvStageMin = 1 << 18;
 // Wavefronts per SIMD the binary64 interpolation kernel with up to 5 fields
 // is held to: three (at most 168 registers; a few bytes of spills at order 7
 // with 5 fields, 12 % faster than two wavefronts on the large box); the
@@ -413,9 +416,10 @@ int run_eval(fp_handle *h, const Work &w, int npts, const int *code, const int *
             l1 = pool_event(h);
             FP_HIP(hipEventRecord(t0, s));
         }
-        // Staged path (matrix-core orders): points grouped by element with the
-        // two-level counting sort, values staged in the grouping's bucket
-        // order and moved to the output by k_ev_unstage.  The grouping's
+        // Staged path (matrix-core orders, passes of at least kEvStageMin
+        // points): points grouped by element with the two-level counting
+        // sort, values staged in the grouping's bucket order and moved to the
+        // output by k_ev_unstage.  The grouping's
         // transient arrays and the staged values live in the pair-results
         // array of the workspace, dead once findpts has returned.  Without
         // that array (the allocation-free entry) or room in it: per-element
@@ -423,7 +427,7 @@ int run_eval(fp_handle *h, const Work &w, int npts, const int *code, const int *
         bool plan_ok = false;
         const GroupPlan gp = group_plan(n, h->E, &plan_ok);
         const int nf_max = nfields < kMaxEvalFields ? nfields : kMaxEvalFields;
-        const bool staged = h->n1 <= kEvMfmaMaxN1 && plan_ok && w.ev_slot &&
+        const bool staged = h->n1 <= kEvMfmaMaxN1 && n >= kEvStageMin && plan_ok && w.ev_slot &&
                             res_bytes >= group_transient_bytes(gp) &&
                             res_bytes >= (size_t)n * nf_max * sizeof(double);
         for (int f0 = 0; f0 < nfields; f0 += kMaxEvalFields) {

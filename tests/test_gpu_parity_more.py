@@ -1,10 +1,11 @@
 """More GPU parity against the CPU oracle (through the C ABI):
 
 * findpts_eval with 4, 5 and 9 fields at orders 7, 9 and 12 -- each order's
-  interpolation kernel, both field passes of the order-7 matrix-core kernel
-  and the split of a call into launches of at most 8 fields -- element by
-  element at 1e-13 max|F|, with crowded elements spread over several work
-  units and not-found points in the mix;
+  interpolation kernel, the split of a call into launches of at most 8
+  fields, and at order 7 (3e5 points) the staged path (grouping by the
+  two-level counting sort, values staged in bucket order and moved to the
+  output) -- element by element at 1e-13 max|F|, with crowded elements
+  spread over several work units and not-found points in the mix;
 * the closest-node start at exact near-ties: points midway between two
   nodes on neighbouring turns of the N = 15 spiral (Section 3.1), where the
   start node decides which local minimum Newton settles in;
@@ -54,7 +55,8 @@ def test_eval_many_fields(dev, N, nf):
     E = mesh.E
     fields, _ = w.poly_fields(mesh, nf, seed=100 + N + nf)
     rng = np.random.default_rng(200 + N + nf)
-    P = 30_001
+    # order 7: above the size where the matrix-core kernel's pass is staged
+    P = 300_001 if N <= 7 else 30_001
     # a crowded element (several work units of every kernel), a spread of
     # the rest, ragged counts, and not-found points
     el = np.where(rng.uniform(size=P) < 0.35, 3, rng.integers(0, E, P)).astype(np.int32)
@@ -87,7 +89,7 @@ def test_eval_many_fields_mixed(dev, N, nf):
     mesh = w.annulus_mesh(2, 8, 2, N=N)
     fields, _ = w.poly_fields(mesh, nf, seed=300 + N + nf)
     rng = np.random.default_rng(400 + N + nf)
-    P = 20_001
+    P = 300_001 if N == 7 else 20_001
     el = np.where(rng.uniform(size=P) < 0.3, 5, rng.integers(0, mesh.E, P)).astype(np.int32)
     rst = rng.uniform(-1, 1, (P, 3))
     code = np.zeros(P, np.int32)
