@@ -256,6 +256,7 @@ void k_eval_mfma(EvArgs a, FieldPtrs F,
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             const double *src = F.f[f] + (long long)e * V;
+            double raw[MBF][S::KB];
 #pragma unroll
             for (int mb = 0; mb < MBF; ++mb) {
                 const int k = mb * S::PPB + pr;
@@ -263,7 +264,24 @@ void k_eval_mfma(EvArgs a, FieldPtrs F,
                 for (int kb = 0; kb < S::KB; ++kb) {
                     const int i = 4 * kb + q;
                     const bool ok = k < N1 && jj < N1 && i < N1;
-                    A[f][mb][kb] = ok ? (T)src[N1 * (jj + N1 * k) + i] : T(0);
+                    if constexpr (sizeof(T) == sizeof(double)) {
+                        raw[mb][kb] = ok ? src[N1 * (jj + N1 * k) + i] : 0.0;
+                    } else {
+                        // binary32: every load is issued unconditionally
+                        // (entries past the element's nodes read its first
+                        // value and are zeroed below), so that the loads are
+                        // in flight together before their conversions wait
+                        raw[mb][kb] = src[ok ? N1 * (jj + N1 * k) + i : 0];
+                    }
+                }
+            }
+#pragma unroll
+            for (int mb = 0; mb < MBF; ++mb) {
+                const int k = mb * S::PPB + pr;
+#pragma unroll
+                for (int kb = 0; kb < S::KB; ++kb) {
+                    const bool ok = k < N1 && jj < N1 && 4 * kb + q < N1;
+                    A[f][mb][kb] = ok ? (T)raw[mb][kb] : T(0);
                 }
             }
         }
