@@ -59,6 +59,8 @@ struct LocArgs {
     int *res_in;
     unsigned *cand_part;  // per k_cand block: the method's candidates (first pass)
     unsigned *iter_part;  // per block: Newton iterations of its pairs
+    int pair_max;         // second pass, orders 1..7: up to this many pairs run on
+                          // k_newton_pair (one wavefront per pair), else 0
 };
 
 __device__ __forceinline__ int cell_of(const Grid &g, int a, double x)
@@ -566,6 +568,7 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
 #include "fp_newton8.inc"
 #include "fp_mixed8.inc"
 #include "fp_newton_pl.inc"
+#include "fp_pair.inc"
 
 constexpr int kStatsBlocks = 32;
 
@@ -759,6 +762,8 @@ static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, int
             *nblk = FP_GRID(kUnitMfma);                                              \
             k_locate_mfma<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_dnode);     \
         }                                                                            \
+        if (a.only && a.pair_max > 0)                                                \
+            k_newton_pair<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis);                 \
     } while (0)
 // orders 8 and 9: matrix cores, one plane per lane; mixed precision (first
 // pass): a binary32 phase, then binary64 Newton from its end points
@@ -878,6 +883,7 @@ int run_findpts(fp_handle *h, const Work &w, int npts, const double *pts, const 
         a.obb = nullptr;
         a.redo = nullptr;
         a.only = w.redo;
+        a.pair_max = h->n1 <= kN8 ? kPairMax : 0;
         FP_HIP(fill_int_gated(w.elem_cnt, 0, (long long)h->E + 1, w.gate, s));
         k_cand<<<pb, 256, 0, s>>>(a);
         FP_HIP(hipGetLastError());
