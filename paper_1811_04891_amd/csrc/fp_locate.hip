@@ -745,13 +745,17 @@ static hipError_t launch_locate_kernel(const fp_handle *h, const LocArgs &a, int
         *nblk = FP_GRID(kUnitScalar);                             \
         k_locate<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_dnode); \
     } while (0)
+// mixed precision: first pass only (the second pass is binary64).  At order 5
+// the binary64 kernel (two wavefronts per SIMD) is faster than the binary32
+// design of orders <= 6, so a mixed-precision handle locates in binary64 there.
+constexpr int kBinary64Only = 6;
 // mixed precision: first pass only (the second pass is binary64)
 #define FP_LAUNCH_MFMA(N1)                                                           \
     do {                                                                             \
         if (h->precision == FP_PREC_MIXED && a.obb && N1 == kN8) {                   \
             *nblk = FP_GRID(kUnitMixed);                                             \
             k_mixed8<<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_basis32, h->d_dnode); \
-        } else if (h->precision == FP_PREC_MIXED && a.obb) {                         \
+        } else if (h->precision == FP_PREC_MIXED && a.obb && N1 != kBinary64Only) {  \
             *nblk = FP_GRID(kUnitMixed);                                             \
             k_locate_mixed<N1><<<*nblk, kWave, 0, s>>>(a, h->d_basis, h->d_basis32,  \
                                                         h->d_dnode);                 \
