@@ -54,7 +54,9 @@ inline GroupPlan group_plan(int n, int K, bool *ok)
     const long long B = ((long long)K + (1LL << g.shift) - 1) >> g.shift;
     g.B = B < 1 ? 1 : (int)B;
     g.T = n < 1 ? 1 : (int)(((long long)n + kGrpTile - 1) / kGrpTile);
-    *ok = g.shift <= kGrpMaxShift;
+    // the scans take int counts
+    const long long gc = ((long long)1 << g.shift) * (g.B + ((long long)n + kGrpChunk - 1) / kGrpChunk);
+    *ok = g.shift <= kGrpMaxShift && gc < 0x7fffffffLL && (long long)g.B * g.T < 0x7fffffffLL;
     return g;
 }
 
