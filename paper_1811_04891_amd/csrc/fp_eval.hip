@@ -1,8 +1,11 @@
 // findpts_eval: tensor-product Lagrange interpolation of nodal fields at
 // located points (Section 2.1 of the paper).  Points are grouped by element
-// with a counting sort so that one 64-lane wavefront reads an element's field
-// values once (scalar loads) for a run of its points (a work unit; an element
-// with many points is spread over several units).
+// (the two-level counting sort of fp_group.h for large passes, atomic
+// per-element counters otherwise) so that a wavefront reads an element's
+// field values once for a run of its points (a work unit; an element with
+// many points is spread over several units).  In large passes at orders
+// <= 7 the values go to a staging array in the grouping's order first and
+// k_ev_unstage moves them to the caller's output with consecutive stores.
 #include <algorithm>
 #include <cmath>
 #include <mutex>
