@@ -9,9 +9,13 @@ For each point (these are readings of points the paper leaves open):
   map, is <= tol * h_e.
 * a code 0 / code 1 flip is accepted only inside the band
   |sqrt(d2) - tol h_e| <= 1e-3 tol h_e.
-* border (code 1): dist2 agrees to 1e-9 relative (+ a (1e-13 h)^2 floor); if
-  the elements differ, the oracle's own Newton on the GPU's element must
-  reach the same distance (a tie between local minima).
+* border (code 1): dist2 agrees to 1e-9 relative plus eps (2 d + eps), with
+  d = sqrt(dist2) and eps = 1e-13 h: each side's binary64 map carries an
+  absolute error of order eps, so two distances d may differ by eps and their
+  squares by eps (2 d + eps), which exceeds the relative term for points
+  closer than about 1e-4 h to the face; if the elements differ, the oracle's
+  own Newton on the GPU's element must reach the same distance (a tie between
+  local minima).
 Integer outputs (code, el) are compared exactly outside these cases.
 """
 import numpy as np
@@ -62,7 +66,8 @@ def compare_locate(om, pts, gpu, ora, h, tol, max_report=5, check_residual_every
     bor = (oc == 1) & (gc == 1)
     for i in np.nonzero(bor)[0]:
         e = oe[i]
-        floor = (1e-13 * h[e]) ** 2
+        eps = 1e-13 * h[e]
+        floor = eps * (2.0 * np.sqrt(od[i]) + eps)
         if abs(gd[i] - od[i]) > 1e-9 * od[i] + floor:
             if ge[i] != oe[i]:
                 _, d2o, _ = om.newton(ge[i], pts[i])
