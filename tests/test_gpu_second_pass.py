@@ -7,10 +7,12 @@ boxes of neighbours whose oriented boxes miss them: the first pass leaves
 them without an inside candidate and with a partial candidate set, and the
 second pass solves the candidates the oriented boxes dropped.  With tens of
 thousands of such points the second pass holds more pairs than the
-one-wavefront-per-pair kernel takes (8,192), so the order's matrix-core
-kernel runs it: binary64, and in mixed precision also resuming the pairs the
-binary32 phase left unsolved or outside.  Checked against the CPU oracle
-under the rules of the other parity tests."""
+one-wavefront-per-pair kernel takes (8,192), so at orders 4 and 7 the
+order's matrix-core kernel runs it: binary64, and in mixed precision also
+resuming the pairs the binary32 phase left unsolved or outside.  Orders 9
+(matrix cores, one plane per lane) and 12 (the scalar kernel) run the same
+long passes on their own kernels.  Checked against the CPU oracle under the
+rules of the other parity tests."""
 import sys
 
 import numpy as np
@@ -78,7 +80,7 @@ def _shell_points(seed):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("N", [4, 7])
+@pytest.mark.parametrize("N", [4, 7, 9, 12])
 def test_long_second_pass(dev, N, prec):
     fp = _fp()
     precision = fp.FP_PREC_MIXED if prec == "mixed" else fp.FP_PREC_FP64
@@ -95,7 +97,9 @@ def test_long_second_pass(dev, N, prec):
     second = pairs - pairs1
     _say(f"pairs {pairs}, first pass {pairs1}, second pass {second}")
     assert npts == len(pts)
-    assert second > PAIR_MAX  # the matrix-core kernel ran the second pass
+    # at orders up to 7 the matrix-core kernel ran the second pass (above
+    # them there is no pair kernel: the order's own kernel always runs it)
+    assert second > PAIR_MAX
     g = (code.cpu().numpy(), el.cpu().numpy(), rst.cpu().numpy(), d2.cpu().numpy())
     om = oracle.OracleMesh.from_mesh(mesh, TOL)
     o = om.findpts(pts.numpy())
