@@ -474,6 +474,12 @@ __device__ __forceinline__ void geo2(cptr<double> X, BasisPtr<double> B, const d
         x[c] = v;
         J[2 * c] = vr;
         J[2 * c + 1] = vs;
+        // the Jacobian is complete here: otherwise its half of the
+        // contraction is sunk past the trust-region acceptance branch, and
+        // the element rows it reads are held (spilled) across that branch
+        FP_KEEP(x[c]);
+        FP_KEEP(J[2 * c]);
+        FP_KEEP(J[2 * c + 1]);
     }
 }
 
