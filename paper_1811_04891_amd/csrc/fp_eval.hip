@@ -220,7 +220,7 @@ __global__ __launch_bounds__(kEvThreads) void k_eval_grp(EvArgs a, FieldPtrs F,
 // is the launch's field count (at most 8), so one pass reads each point's r
 // and evaluates its basis once for all fields, and no register holds the
 // fragments of a field the launch does not have.
-constexpr int kUnitEvalMfma = 512;  // points of one element per work unit
+constexpr int kUnitEvalMfma = 256;  // points of one element per work unit
 constexpr int kEvMfmaMaxN1 = 8;      // orders with the matrix-core kernel
 // Smallest pass that takes the staged path: below it the grouping's launches
 // cost more than the scattered stores they avoid.

@@ -196,17 +196,26 @@ struct UnitList {
     {
         return off[s * gs < ne ? s * gs : ne];
     }
-    __host__ __device__ __forceinline__ bool at(long long u, Unit &U) const
+    // Unit u of the list (false for a gap).  Called by every lane of a
+    // wavefront with the same u (converged code, full wavefront): the 64
+    // lanes probe 64 evenly spaced segments of the bracket at once, and the
+    // prefix of probes with s + b(s) / K <= u (a prefix, since that sum grows
+    // with s) narrows the bracket to one 64th per round, so a list of T
+    // windows takes log64 T dependent loads instead of log2 T.
+    __device__ __forceinline__ bool at(long long u, Unit &U) const
     {
-        long long lo = u - T, hi = u;
+        long long lo = u - T, hi = u;  // s + b(s) / K <= u holds at lo
         if (lo < 0) lo = 0;
         if (hi > ns - 1) hi = ns - 1;
+        const long long lane = (long long)(threadIdx.x & (kWave - 1));
         while (lo < hi) {
-            const long long mid = (lo + hi + 1) >> 1;
-            if (mid + b(mid) / K <= u)
-                lo = mid;
-            else
-                hi = mid - 1;
+            const long long span = hi - lo;
+            const long long p = lo + ((lane + 1) * span + kWave - 1) / kWave;  // in (lo, hi]
+            const long long cnt = __popcll(__ballot(p + b(p) / K <= u));
+            const long long nlo = cnt == 0 ? lo : lo + (cnt * span + kWave - 1) / kWave;
+            const long long nhi = cnt == kWave ? hi : lo + ((cnt + 1) * span + kWave - 1) / kWave - 1;
+            lo = nlo;
+            hi = nhi;
         }
         const int b0 = b(lo), b1 = b(lo + 1);
         const long long j = u - lo;
