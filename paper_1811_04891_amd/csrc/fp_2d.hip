@@ -603,7 +603,7 @@ __global__ __launch_bounds__(kWave) void k2_locate(Loc2 a, const double *__restr
     const BasisPtr<double> B{as_const(basis)};
     unsigned long long my_iters = 0;
     const UnitList units(a.elem_off, a.E, 1, a.E, kUnit2);
-    for (long long u = blockIdx.x; u < units.end; u += gridDim.x) {
+    for (long long u = xcd_unit(blockIdx.x, gridDim.x); u < units.end; u += gridDim.x) {
         Unit U;
         if (!units.at(u, U)) continue;
         const int e = U.seg;
@@ -843,7 +843,7 @@ __global__ __launch_bounds__(kWave) void k2_eval(Ev2 a, const double *__restrict
     constexpr int V = N1 * N1;
     const BasisPtr<double> B{as_const(basis)};
     const UnitList units(a.off, a.E, 1, a.E, kUnitEval2);
-    for (long long u = blockIdx.x; u < units.end; u += gridDim.x) {
+    for (long long u = xcd_unit(blockIdx.x, gridDim.x); u < units.end; u += gridDim.x) {
         Unit U;
         if (!units.at(u, U)) continue;
         const int e = U.seg;

@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kWave) void k_eval(EvArgs a, FieldPtrs F, const dou
     constexpr int V = N1 * N1 * N1;
     const BasisPtr<double> B{as_const(basis)};
     const UnitList units(a.off, a.E, 1, a.E, kUnitEval);
-    for (long long unit = blockIdx.x; unit < units.end; unit += gridDim.x) {
+    for (long long unit = xcd_unit(blockIdx.x, gridDim.x); unit < units.end; unit += gridDim.x) {
         Unit U;
         if (!units.at(unit, U)) continue;
         const int e = U.seg, beg = U.beg, end = U.end;
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(kEvThreads) void k_eval_grp(EvArgs a, FieldPtrs F,
     const BasisPtr<double> B{as_const(basis)};
     const int ns = (a.E + G - 1) / G;
     const UnitList units(a.off, ns, G, a.E, kUnitGrp);
-    for (long long unit = blockIdx.x; unit < units.end; unit += gridDim.x) {
+    for (long long unit = xcd_unit(blockIdx.x, gridDim.x); unit < units.end; unit += gridDim.x) {
         Unit U;
         if (!units.at(unit, U)) continue;  // uniform
         const int e0 = U.seg * G;
@@ -246,7 +246,7 @@ void k_eval_mfma(EvArgs a, FieldPtrs F,
     LaneNodes<N1, T> Z;  // h_i(r), h_j(s) only for the lane's own i, j = g + 4 w
     lane_nodes<N1, T>(B, threadIdx.x >> 4, Z);
     const UnitList units(a.off, a.E, 1, a.E, kUnitEvalMfma);
-    for (long long unit = blockIdx.x; unit < units.end; unit += gridDim.x) {
+    for (long long unit = xcd_unit(blockIdx.x, gridDim.x); unit < units.end; unit += gridDim.x) {
         Unit U;
         if (!units.at(unit, U)) continue;
         const int e = U.seg, beg = U.beg, end = U.end;

@@ -30,6 +30,21 @@ __device__ __forceinline__ int xcd_block(int b, int G)
     return x * q + (x < r ? x : r) + i;
 }
 
+// Unit walked first by block b of a grid of G blocks (blocks go to the dies
+// in turn, b mod kXcds): each die takes runs of kXcdRun consecutive units,
+// the runs of the dies interleaved, so that the units of a crowded element
+// (consecutive indices) mostly share one die's L2 while the work stays spread
+// over all dies.  A bijection of [0, G) (the last partial round of runs
+// keeps b).
+constexpr int kXcdRun = 8;
+__device__ __forceinline__ long long xcd_unit(long long b, long long G)
+{
+    constexpr long long P = (long long)kXcds * kXcdRun;
+    if (b >= (G / P) * P) return b;
+    const long long i = b / kXcds, x = b % kXcds;
+    return (i / kXcdRun) * P + x * kXcdRun + i % kXcdRun;
+}
+
 // GLL nodes z_i and barycentric weights wb_i = 1 / prod_{m != i} (z_i - z_m),
 // passed to kernels by value (kernel arguments are read through the scalar
 // cache).

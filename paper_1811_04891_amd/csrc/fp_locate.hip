@@ -509,7 +509,7 @@ __global__ __launch_bounds__(kWave) void k_locate(LocArgs a, const double *__res
     const BasisPtr<double> B{as_const(basis)};
     unsigned long long my_iters = 0;
     const UnitList units(a.elem_off, a.E, 1, a.E, kUnitScalar);
-    for (long long u = blockIdx.x; u < units.end; u += gridDim.x) {
+    for (long long u = xcd_unit(blockIdx.x, gridDim.x); u < units.end; u += gridDim.x) {
         Unit U;
         if (!units.at(u, U)) continue;
         const int e = U.seg;
