@@ -82,6 +82,10 @@ __global__ __launch_bounds__(256) void k_ev_scatter(EvArgs a)
 // values (its stage row is its index in the grouping's bucket order, so the
 // rows of a grouping tile's points lie in a few runs) and the stores of
 // consecutive points are consecutive.  Points that were not found get NaN.
+// One instance per field count: the row's NF loads are issued together
+// before any store (the stores could alias the stage for all the compiler
+// knows, so loads and stores taken in turn would wait on each load).
+template <int NF>
 __global__ __launch_bounds__(256) void k_ev_unstage(EvArgs a)
 {
     // the blocks of one grouping tile run on one die, whose L2 then holds
@@ -89,12 +93,31 @@ __global__ __launch_bounds__(256) void k_ev_unstage(EvArgs a)
     const int p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (p >= a.npts) return;
     const int j = a.pos[p];
+    double v[NF];
     if (j < 0) {
-        for (int f = 0; f < a.nf; ++f) a.out[f * a.ostride + p] = NAN;
-        return;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) v[f] = NAN;
+    } else {
+        const double *src = a.stage + (long long)j * NF;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) v[f] = src[f];
     }
-    const double *src = a.stage + (long long)j * a.nf;
-    for (int f = 0; f < a.nf; ++f) a.out[f * a.ostride + p] = src[f];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) a.out[f * a.ostride + p] = v[f];
+}
+
+static void launch_unstage(const EvArgs &a, int nblk, hipStream_t s)
+{
+    switch (a.nf) {
+        case 1: k_ev_unstage<1><<<nblk, 256, 0, s>>>(a); break;
+        case 2: k_ev_unstage<2><<<nblk, 256, 0, s>>>(a); break;
+        case 3: k_ev_unstage<3><<<nblk, 256, 0, s>>>(a); break;
+        case 4: k_ev_unstage<4><<<nblk, 256, 0, s>>>(a); break;
+        case 5: k_ev_unstage<5><<<nblk, 256, 0, s>>>(a); break;
+        case 6: k_ev_unstage<6><<<nblk, 256, 0, s>>>(a); break;
+        case 7: k_ev_unstage<7><<<nblk, 256, 0, s>>>(a); break;
+        default: k_ev_unstage<8><<<nblk, 256, 0, s>>>(a); break;
+    }
 }
 
 // One wavefront per work unit: up to kUnitEval points of one element, 64 at a
@@ -496,7 +519,7 @@ int run_eval(fp_handle *h, const Work &w, int npts, const int *code, const int *
             FP_HIP(launch_eval_kernel(h->n1, h->E, n, a, F, h->d_basis, h->d_basis32,
                                       h->precision == FP_PREC_MIXED, s));
             if (staged) {
-                k_ev_unstage<<<pb, 256, 0, s>>>(a);
+                launch_unstage(a, pb, s);
                 FP_HIP(hipGetLastError());
             }
         }
