@@ -773,7 +773,7 @@ constexpr int kBinary64Only = 6;
 // pass): a binary32 phase, then binary64 Newton from its end points
 #define FP_LAUNCH_PL(N1)                                                              \
     do {                                                                              \
-        *nblk = FP_GRID(kUnitMfma);                                                   \
+        *nblk = FP_GRID(kUnitPl);                                                     \
         if (h->precision == FP_PREC_MIXED && a.obb) {                                 \
             k_mixed_pl<N1><<<*nblk, 2 * kWave, 0, s>>>(a, h->d_basis32, h->d_dnode); \
             k_newton_pl<N1, true><<<*nblk, 2 * kWave, 0, s>>>(a, h->d_basis, h->d_basis32, \
